@@ -1,0 +1,393 @@
+"""The F-statistic, exact and by the resampling method, in FP64 (oracle; test
+infrastructure only -- see the package docstring).
+
+Paper: Sec. III A (Eqs. OS, Fab: the F-statistic), Sec. VI A (Eqs. pham, phas,
+Far, Bt, ia: barycentric resampling; nearest-neighbour and two-step Fourier +
+spline interpolation), Sec. VI B (Eq. DFT).
+
+Readings of points the paper leaves open (all listed in the design doc):
+
+R-norm   Normalisation.  For white noise of per-sample variance sigma^2 the
+         one-sided PSD is S0 = 2 sigma^2 dt and the integrals of Eqs. (Fab) are
+         dt times sums, so Eq. (OS) becomes
+             F = |S_a|^2/(sigma^2 A) + |S_b|^2/(sigma^2 B),
+         with S_a = sum m x a e^{-i phi}, A = sum m a^2, B = sum m b^2 over the
+         detector samples (m = gap mask).  Where a gap mask breaks the
+         whole-sidereal-day assumption that makes <ab> vanish (Sec. III A), the
+         same maximum-likelihood projection with C = sum m a b is used:
+             F = (B|S_a|^2 + A|S_b|^2 - 2C Re(S_a S_b*)) / (sigma^2 (AB - C^2)),
+         which equals the Eq. (OS) form exactly when C = 0.
+R-band   The data are real, narrow-band, heterodyned: band-relative frequency f
+         in [0, 1/(2 dt)), physical frequency f_ref + f.  omega_0 = 2 pi (f_ref+f)
+         enters the Roemer term of Eq. (pha3).
+R-grid   SSB time grid: t_b0 = t_b(0) = phi_m(0), t_b_j = t_b0 + j dt,
+         j = 0..N-1 (the same number of points as the data, Sec. VI A).
+         The resampled value is 0 where t(t_b) falls outside [0, (N-1) dt].
+R-interp Only x is interpolated; a(t), b(t) and the demodulation phase are
+         evaluated exactly at t(t_b_j) (Eq. ia read literally).  Nearest
+         neighbour takes x[floor(u + 1/2)], u = t/dt.  The two-step method
+         upsamples x by 2 by zero-padding its DFT (the Nyquist bin of an even N
+         split equally between +N/2 and -N/2), then interpolates the 2N-point
+         series by a degree-1 spline (LINEAR_UP2) or by the periodic cubic
+         spline (CUBIC_UP2; the Fourier interpolant is periodic with period 2N
+         samples, so the periodic end condition is the consistent one).
+R-jac    The Jacobian dt/dt_b is dropped, as in Eq. (ia).
+R-f0     The frequency term e^{-2 pi i f t_b0} common to S_a and S_b is
+         dropped; it does not change F.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from typing import Optional
+
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from . import model, sums
+
+NEAREST, LINEAR_UP2, CUBIC_UP2 = 0, 1, 2
+
+
+@dataclass
+class Segment:
+    """One data segment (mirrors the fields of the C-ABI segment description)."""
+    x: np.ndarray
+    dt: float
+    n_days: int
+    t0: float = 0.0
+    mask: Optional[np.ndarray] = None
+    f_ref: float = 435.1875
+    sigma2: float = 1.0
+    nfft: int = 0
+    _cache: dict = field(default_factory=dict, repr=False)
+
+    @property
+    def n(self) -> int:
+        return int(np.asarray(self.x).size)
+
+    @property
+    def m(self) -> np.ndarray:
+        return (np.ones(self.n) if self.mask is None
+                else (np.asarray(self.mask) != 0).astype(np.float64))
+
+    @property
+    def xm(self) -> np.ndarray:
+        """Data with gaps zeroed."""
+        return np.asarray(self.x, dtype=np.float64) * self.m
+
+    @property
+    def fft_len(self) -> int:
+        if self.nfft:
+            return int(self.nfft)
+        return 1 << int(math.ceil(math.log2(2 * self.n)))
+
+    def noise_var(self) -> float:
+        """sigma^2: the caller's value, or (if <= 0) the unbiased sample
+        variance of the samples outside gaps."""
+        if self.sigma2 > 0:
+            return float(self.sigma2)
+        v = np.asarray(self.x, dtype=np.float64)[self.m != 0]
+        return float(np.sum((v - v.mean()) ** 2) / (v.size - 1))
+
+
+# --------------------------------------------------------------------------
+# Barycentric time (Eq. Bt) and its inversion
+# --------------------------------------------------------------------------
+def ssb_times(seg: Segment, alpha, delta, det, eph, tol=1e-12, max_iter=60):
+    """Returns (t_b0, t) with t_j the detector time whose barycentric time
+    t + phi_m(t) equals t_b0 + j dt.  Fixed-point iteration
+    t <- t_b - phi_m(t), a contraction because |phi_m'| << 1."""
+    j = np.arange(seg.n, dtype=np.float64)
+    tb0 = float(model.roemer_delay(seg.t0, alpha, delta, det, eph))
+    tb = tb0 + j * seg.dt
+    t = j * seg.dt
+    for _ in range(max_iter):
+        t_new = tb - model.roemer_delay(seg.t0 + t, alpha, delta, det, eph)
+        done = np.max(np.abs(t_new - t)) < tol
+        t = t_new
+        if done:
+            break
+    return tb0, t
+
+
+# --------------------------------------------------------------------------
+# Interpolation (Sec. VI A)
+# --------------------------------------------------------------------------
+def fourier_upsample(x):
+    """2x upsampling by zero-padding the DFT: returns y with 2N points,
+    y[2m] = x[m] (Sec. VI A, first step of the two-step method)."""
+    x = np.asarray(x, dtype=np.float64)
+    n = x.size
+    X = np.fft.fft(x)
+    Y = np.zeros(2 * n, dtype=np.complex128)
+    h = n // 2
+    if n % 2 == 0:
+        Y[:h] = X[:h]
+        Y[h] = 0.5 * X[h]
+        Y[2 * n - h] = 0.5 * X[h]
+        Y[2 * n - h + 1:] = X[h + 1:]
+    else:
+        Y[:h + 1] = X[:h + 1]
+        Y[2 * n - h:] = X[h + 1:]
+    return 2.0 * np.fft.ifft(Y).real
+
+
+def periodic_spline_m(y):
+    """Second derivatives M of the periodic cubic spline through (i, y_i),
+    i = 0..P-1 with period P: the cyclic system
+        M_{i-1} + 4 M_i + M_{i+1} = 6 (y_{i-1} - 2 y_i + y_{i+1})."""
+    y = np.asarray(y, dtype=np.float64)
+    p = y.size
+    i = np.arange(p)
+    rows = np.concatenate([i, i, i])
+    cols = np.concatenate([i, (i - 1) % p, (i + 1) % p])
+    vals = np.concatenate([np.full(p, 4.0), np.ones(p), np.ones(p)])
+    A = sp.csc_matrix((vals, (rows, cols)), shape=(p, p))
+    rhs = 6.0 * (np.roll(y, 1) - 2.0 * y + np.roll(y, -1))
+    return spla.spsolve(A, rhs)
+
+
+def _upsampled(seg: Segment, mode):
+    key = ("up", mode)
+    if key not in seg._cache:
+        y = fourier_upsample(seg.xm)
+        M = periodic_spline_m(y) if mode == CUBIC_UP2 else None
+        seg._cache[key] = (y, M)
+    return seg._cache[key]
+
+
+def interpolate(seg: Segment, u, mode):
+    """x at fractional sample positions u (0 outside [0, N-1]), and dx/du."""
+    u = np.asarray(u, dtype=np.float64)
+    n = seg.n
+    valid = (u >= 0.0) & (u <= n - 1)
+    uu = np.where(valid, u, 0.0)
+    xr = np.zeros_like(u)
+    dxdu = np.zeros_like(u)
+    if mode == NEAREST:
+        idx = np.floor(uu + 0.5).astype(np.int64)
+        xr = np.where(valid, seg.xm[np.minimum(idx, n - 1)], 0.0)
+        return xr, dxdu
+    y, M = _upsampled(seg, mode)
+    v = 2.0 * uu
+    i = np.minimum(np.floor(v).astype(np.int64), 2 * n - 2)
+    s = v - i
+    y0, y1 = y[i], y[i + 1]
+    if mode == LINEAR_UP2:
+        val = (1.0 - s) * y0 + s * y1
+        dv = y1 - y0
+    elif mode == CUBIC_UP2:
+        m0, m1 = M[i], M[i + 1]
+        r = 1.0 - s
+        val = r * y0 + s * y1 + ((r ** 3 - r) * m0 + (s ** 3 - s) * m1) / 6.0
+        dv = y1 - y0 + ((1.0 - 3.0 * r * r) * m0 + (3.0 * s * s - 1.0) * m1) / 6.0
+    else:
+        raise ValueError("unknown interpolation mode %r" % (mode,))
+    xr = np.where(valid, val, 0.0)
+    dxdu = np.where(valid, 2.0 * dv, 0.0)
+    return xr, dxdu
+
+
+# --------------------------------------------------------------------------
+# The resampled, demodulated series (Eq. ia) and the F-statistic
+# --------------------------------------------------------------------------
+def resampled(seg: Segment, alpha, delta, det, eph, mode):
+    """Everything the method needs on the uniform SSB grid for one sky point."""
+    tb0, t = ssb_times(seg, alpha, delta, det, eph)
+    u = t / seg.dt
+    xr, dxdu = interpolate(seg, u, mode)
+    a, b = model.amplitude_modulation(seg.t0 + t, alpha, delta, det, eph)
+    pm = model.roemer_delay(seg.t0 + t, alpha, delta, det, eph)
+    return dict(tb0=tb0, t=t, u=u, xr=xr, dxdu=dxdu, a=a, b=b, pm=pm)
+
+
+def demod_cycles(t, pm, f_ref, fdot):
+    """Frequency-independent part of the phase on the resampled grid, cycles:
+    f_ref phi_m + fdot (t^2/2 + phi_m t)  (Eq. phas plus the f_ref part of
+    omega_0 phi_m that the band-relative FFT does not absorb)."""
+    return f_ref * pm + fdot * (0.5 * t * t + pm * t)
+
+
+def demodulated(seg: Segment, fdot, alpha, delta, det, eph, mode):
+    """z_a, z_b on the SSB grid: x(t(t_b)) a(t(t_b)) e^{-i phi_s(t(t_b))}."""
+    r = resampled(seg, alpha, delta, det, eph, mode)
+    cyc = demod_cycles(r["t"], r["pm"], seg.f_ref, fdot)
+    e = np.exp(-2j * math.pi * (cyc - np.round(cyc)))
+    return r["xr"] * r["a"] * e, r["xr"] * r["b"] * e
+
+
+def abc(seg: Segment, alpha, delta, det, eph):
+    """A, B, C = sums of m a^2, m b^2, m a b over the detector samples."""
+    t = np.arange(seg.n, dtype=np.float64) * seg.dt
+    a, b = model.amplitude_modulation(seg.t0 + t, alpha, delta, det, eph)
+    m = seg.m
+    return float(np.sum(m * a * a)), float(np.sum(m * b * b)), float(np.sum(m * a * b))
+
+
+def combine(Sa, Sb, A, B, C, sigma2):
+    """F from the two correlations (reading R-norm; Eq. OS when C = 0)."""
+    Sa = np.asarray(Sa)
+    Sb = np.asarray(Sb)
+    num = B * np.abs(Sa) ** 2 + A * np.abs(Sb) ** 2 - 2.0 * C * np.real(Sa * np.conj(Sb))
+    return num / (sigma2 * (A * B - C * C))
+
+
+def fstat_bins(seg: Segment, fdot, alpha, delta, det, eph, mode, k=None, dft="direct"):
+    """F on Fourier bins k (default: all of [0, nfft/2)) by the resampling
+    method.  dft='direct' sums the DFT term by term; dft='fft' uses numpy's
+    FP64 FFT of the zero-padded series for the same sums."""
+    nfft = seg.fft_len
+    if k is None:
+        k = np.arange(nfft // 2, dtype=np.int64)
+    k = np.asarray(k, dtype=np.int64)
+    za, zb = demodulated(seg, fdot, alpha, delta, det, eph, mode)
+    if dft == "direct":
+        Sa, Sb = sums.dft_bins(za, nfft, k), sums.dft_bins(zb, nfft, k)
+    elif dft == "fft":
+        Sa, Sb = np.fft.fft(za, nfft)[k], np.fft.fft(zb, nfft)[k]
+    else:
+        raise ValueError(dft)
+    A, B, C = abc(seg, alpha, delta, det, eph)
+    return combine(Sa, Sb, A, B, C, seg.noise_var())
+
+
+def fstat_exact(seg: Segment, f, fdot, alpha, delta, det, eph):
+    """F by direct summation of Eqs. (Fab) on the detector samples, at the
+    band-relative frequencies f (no resampling, no FFT)."""
+    t = np.arange(seg.n, dtype=np.float64) * seg.dt
+    pm = model.roemer_delay(seg.t0 + t, alpha, delta, det, eph)
+    a, b = model.amplitude_modulation(seg.t0 + t, alpha, delta, det, eph)
+    w = seg.xm
+    tau = t + pm
+    psi = seg.f_ref * pm + fdot * (0.5 * t * t + pm * t)
+    Sa, Sb = sums.phase_sums(w * a, w * b, tau, psi, f)
+    A, B, C = abc(seg, alpha, delta, det, eph)
+    return combine(Sa, Sb, A, B, C, seg.noise_var())
+
+
+# --------------------------------------------------------------------------
+# Continuous frequency and the analytic gradient
+# --------------------------------------------------------------------------
+def _roemer_partials(T, alpha, delta, det, eph):
+    """phi_m and its partials d/dalpha, d/ddelta, d/dT (seconds, s/rad, 1)."""
+    xes, yes = model.earth_center(T, eph)
+    xe, ye, ze = model.site_vector(T, det, eph)
+    ang = eph.orbit_omega * np.asarray(T, dtype=np.float64) + eph.orbit_phase0
+    th = model.sidereal_angle(T, det, eph)
+    wr = 2.0 * math.pi / eph.sidereal_day
+    dxes = -eph.orbit_radius * eph.orbit_omega * np.sin(ang)
+    dyes = eph.orbit_radius * eph.orbit_omega * np.cos(ang)
+    dxe = -det.radius * math.cos(det.lat) * wr * np.sin(th)
+    dye = det.radius * math.cos(det.lat) * wr * np.cos(th)
+    ca, sa = math.cos(alpha), math.sin(alpha)
+    cd, sd = math.cos(delta), math.sin(delta)
+    ce, se = math.cos(eph.obliquity), math.sin(eph.obliquity)
+    c = model.C_LIGHT
+    pm = (ca * cd * (xes + xe) + (sa * cd * ce + sd * se) * yes + sa * cd * ye + sd * ze) / c
+    d_al = (-sa * cd * (xes + xe) + ca * cd * ce * yes + ca * cd * ye) / c
+    d_de = (-ca * sd * (xes + xe) + (-sa * sd * ce + cd * se) * yes - sa * sd * ye + cd * ze) / c
+    d_T = (ca * cd * (dxes + dxe) + (sa * cd * ce + sd * se) * dyes + sa * cd * dye) / c
+    return pm, d_al, d_de, d_T
+
+
+def _ab_partials(T, alpha, delta, det, eph):
+    """a, b and their partials w.r.t. x = alpha - sidereal angle and delta."""
+    x = alpha - model.sidereal_angle(T, det, eph)
+    ca, cb = model._ab_coeffs(delta, det)
+    g2, lam = 2.0 * det.gamma, det.lat
+    s2g, c2g = math.sin(g2), math.cos(g2)
+    sl, cl = math.sin(lam), math.cos(lam)
+    s2l, c2l = math.sin(2 * lam), math.cos(2 * lam)
+    sd, cd = math.sin(delta), math.cos(delta)
+    s2d, c2d = math.sin(2 * delta), math.cos(2 * delta)
+    # d/ddelta of the coefficients
+    da = dict(a2c=s2g * (3 - c2l) * 2 * s2d / 16.0, a2s=-c2g * sl * 2 * s2d / 4.0,
+              a1c=s2g * s2l * 2 * c2d / 4.0, a1s=-c2g * cl * 2 * c2d / 2.0,
+              a0=-0.75 * s2g * cl * cl * s2d)
+    db = dict(b2c=c2g * sl * cd, b2s=s2g * (3 - c2l) * cd / 4.0,
+              b1c=-c2g * cl * sd, b1s=-s2g * s2l * sd / 2.0)
+    c2x, s2x, c1x, s1x = np.cos(2 * x), np.sin(2 * x), np.cos(x), np.sin(x)
+
+    def ev(k, pre):
+        v = k[pre + "2c"] * c2x + k[pre + "2s"] * s2x + k[pre + "1c"] * c1x + k[pre + "1s"] * s1x
+        return v + k.get(pre + "0", 0.0)
+
+    def evx(k, pre):
+        return (-2 * k[pre + "2c"] * s2x + 2 * k[pre + "2s"] * c2x
+                - k[pre + "1c"] * s1x + k[pre + "1s"] * c1x)
+
+    return ev(ca, "a"), ev(cb, "b"), evx(ca, "a"), evx(cb, "b"), ev(da, "a"), ev(db, "b")
+
+
+def fstat_continuous(seg: Segment, params, det, eph, mode, grad=False):
+    """F at a continuous band-relative frequency by the resampling method
+    (the sum over the SSB grid with e^{-2 pi i f j dt} in place of the FFT
+    kernel), and optionally its analytic gradient dF/d(f, fdot, alpha, delta).
+
+    The gradient differentiates every step: t_b0(alpha, delta); t_j through
+    the implicit relation t_j + phi_m(t_j) = t_b0 + j dt; the interpolant
+    (NEAREST has zero derivative); a(t_j), b(t_j); the demodulation phase; and
+    A, B, C."""
+    f, fdot, alpha, delta = (float(v) for v in params)
+    n, dt = seg.n, seg.dt
+    j = np.arange(n, dtype=np.float64)
+    tb0, t = ssb_times(seg, alpha, delta, det, eph)
+    T = seg.t0 + t
+    xr, dxdu = interpolate(seg, t / dt, mode)
+    pm, pm_al, pm_de, pm_T = _roemer_partials(T, alpha, delta, det, eph)
+    a, b, a_x, b_x, a_d, b_d = _ab_partials(T, alpha, delta, det, eph)
+    cyc = demod_cycles(t, pm, seg.f_ref, fdot) + f * j * dt
+    e = np.exp(-2j * math.pi * (cyc - np.round(cyc)))
+    Sa = np.sum(xr * a * e)
+    Sb = np.sum(xr * b * e)
+    A, B, C = abc(seg, alpha, delta, det, eph)
+    s2 = seg.noise_var()
+    F = float(combine(Sa, Sb, A, B, C, s2))
+    if not grad:
+        return F
+    # d t_b0 / d(alpha, delta)
+    _, tb0_al, tb0_de, _ = _roemer_partials(np.array([seg.t0]), alpha, delta, det, eph)
+    wr = 2.0 * math.pi / eph.sidereal_day
+    den = 1.0 + pm_T
+    dS = {}
+    for name in ("f", "fdot", "alpha", "delta"):
+        if name in ("alpha", "delta"):
+            pm_th = pm_al if name == "alpha" else pm_de
+            tb0_th = float((tb0_al if name == "alpha" else tb0_de)[0])
+            dt_th = (tb0_th - pm_th) / den                       # d t_j / d theta
+            dxr = dxdu * dt_th / dt
+            dx = (1.0 if name == "alpha" else 0.0) - wr * dt_th  # d x / d theta
+            da = a_x * dx + (a_d if name == "delta" else 0.0)
+            db = b_x * dx + (b_d if name == "delta" else 0.0)
+            dpm = pm_th + pm_T * dt_th                            # total d phi_m
+            dcyc = seg.f_ref * dpm + fdot * (t * dt_th + dpm * t + pm * dt_th)
+        else:
+            dxr = da = db = 0.0
+            dcyc = (j * dt) if name == "f" else (0.5 * t * t + pm * t)
+        g = -2j * math.pi * dcyc
+        dS[name] = (np.sum((dxr * a + xr * da + xr * a * g) * e),
+                    np.sum((dxr * b + xr * db + xr * b * g) * e))
+    # d(A, B, C) on the detector grid
+    td = seg.t0 + np.arange(n, dtype=np.float64) * dt
+    ga, gb, gax, gbx, gad, gbd = _ab_partials(td, alpha, delta, det, eph)
+    m = seg.m
+    dABC = {"f": (0.0, 0.0, 0.0), "fdot": (0.0, 0.0, 0.0),
+            "alpha": (np.sum(m * 2 * ga * gax), np.sum(m * 2 * gb * gbx),
+                      np.sum(m * (gax * gb + ga * gbx))),
+            "delta": (np.sum(m * 2 * ga * gad), np.sum(m * 2 * gb * gbd),
+                      np.sum(m * (gad * gb + ga * gbd)))}
+    D = s2 * (A * B - C * C)
+    num = B * abs(Sa) ** 2 + A * abs(Sb) ** 2 - 2 * C * np.real(Sa * np.conj(Sb))
+    out = []
+    for name in ("f", "fdot", "alpha", "delta"):
+        dSa, dSb = dS[name]
+        dA, dB, dC = dABC[name]
+        dnum = (dB * abs(Sa) ** 2 + 2 * B * np.real(np.conj(Sa) * dSa)
+                + dA * abs(Sb) ** 2 + 2 * A * np.real(np.conj(Sb) * dSb)
+                - 2 * dC * np.real(Sa * np.conj(Sb))
+                - 2 * C * np.real(dSa * np.conj(Sb) + Sa * np.conj(dSb)))
+        dD = s2 * (dA * B + A * dB - 2 * C * dC)
+        out.append(float(dnum / D - num * dD / (D * D)))
+    return F, np.array(out)

@@ -1,0 +1,228 @@
+/* fstat.h -- coherent F-statistic over a grid of sky positions and spindowns,
+ * on one AMD Instinct MI355X (gfx950).
+ *
+ * The method is the narrow-band all-sky search of Astone, Borkowski,
+ * Jaranowski, Krolak and Pietka, "Data analysis of gravitational-wave signals
+ * from spinning neutron stars. V": for every grid node (sky position alpha,
+ * delta and spindown fdot) the data are demodulated and resampled to the
+ * solar-system-barycentre time (Sec. VI A, Eqs. Bt and ia), multiplied by the
+ * amplitude-modulation functions a(t), b(t) (Sec. II, Eq. patt), Fourier
+ * transformed (Sec. VI B, Eq. DFT) into the two correlations F_a, F_b of
+ * Eqs. (Fab), and combined into the F-statistic of Eq. (OS) on every Fourier
+ * bin of the band.
+ *
+ * Conventions
+ *   - Every call returns fstat_status: FSTAT_OK (0) or a negative error code.
+ *     Arguments are validated before any device work; on error nothing is
+ *     launched and the outputs are left untouched.  No call aborts, throws or
+ *     exits.
+ *   - Pointers marked "host" are read during the call and may be freed when it
+ *     returns.  Pointers marked "device" are device memory of the plan's GPU,
+ *     owned by the caller (e.g. torch tensors); the library writes them
+ *     asynchronously on the caller's stream (hip_stream = hipStream_t, NULL for
+ *     the default stream).
+ *   - A plan is immutable after creation, except for its workspace; calls on
+ *     one plan must not overlap in time (they share the workspace): serialise
+ *     them on one stream.
+ *   - Frequencies are band-relative: the data are real narrow-band samples of
+ *     the band [f_ref, f_ref + 1/(2 dt)); a band-relative frequency f is the
+ *     physical frequency f_ref + f.  Bin k of an nfft-point transform is
+ *     f_k = k / (nfft dt); the bins of the band are 0 <= k < nfft/2.
+ *   - Times: t is segment time in seconds (0 at the first sample, which is also
+ *     the spindown reference time, Eq. pha3); the ephemeris clock is
+ *     T = t0 + t.
+ */
+#ifndef FSTAT_H
+#define FSTAT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t fstat_status;
+#define FSTAT_OK 0
+#define FSTAT_EINVAL (-1)        /* a null pointer, a size or a value out of range */
+#define FSTAT_ENOTINTDAYS (-2)   /* n dt is not n_sidereal_days sidereal days (within dt/2) */
+#define FSTAT_ENOMEM (-3)        /* device or pinned-host allocation failed */
+#define FSTAT_EDEVICE (-4)       /* a HIP runtime call failed (no device, launch error) */
+#define FSTAT_EUNSUPPORTED (-5)  /* valid but not supported: nfft not a power of two in
+                                    [2^10, 2^22] or below n; n below 16 */
+
+/* Interpolation used to resample onto the barycentric time grid (Sec. VI A). */
+#define FSTAT_NEAREST 0     /* nearest neighbour ("stroboscopic") resampling */
+#define FSTAT_LINEAR_UP2 1  /* two-step: 2x Fourier upsampling, then a degree-1 spline */
+#define FSTAT_CUBIC_UP2 2   /* two-step: 2x Fourier upsampling, then the periodic cubic spline */
+
+/* Arithmetic of the node path.  In both modes the barycentric time, the Roemer
+ * delay and the demodulation phase are evaluated in FP64. */
+#define FSTAT_FP32 0  /* resampled data, FFTs and F combination in FP32 */
+#define FSTAT_FP64 1  /* everything in FP64 */
+
+/* Output modes of fstat_grid. */
+#define FSTAT_OUT_MAP 0        /* F on every bin of [k_lo, k_hi) */
+#define FSTAT_OUT_MAX 1        /* per node: the largest F in [k_lo, k_hi) and its bin */
+#define FSTAT_OUT_CROSSINGS 2  /* every (node, bin) with F above a threshold */
+
+/* Detector (Sec. II; Sec. V for the Earth radius). Angles in radians. */
+typedef struct {
+  double lat_rad;    /* geodetic latitude */
+  double lon_rad;    /* east longitude */
+  double gamma_rad;  /* arm bisector, measured counter-clockwise from local East */
+  double zeta_rad;   /* angle between the arms (pi/2); only scales injected signals */
+  double radius_m;   /* distance of the site from the Earth's centre (spherical Earth) */
+} fstat_detector;
+
+/* Analytic ephemeris standing in for the DE405-based astrometry of Sec. V: the
+ * Earth's centre on a circular orbit in the ecliptic plane (the R_ES term of
+ * Eq. pha5), the site rotating at the sidereal rate (the R_E term). */
+typedef struct {
+  double obliquity_rad;    /* obliquity of the ecliptic, Eq. (pha4) */
+  double orbit_radius_m;   /* SSB -> Earth-centre distance */
+  double orbit_omega;      /* orbital angular rate, rad/s */
+  double orbit_phase0;     /* orbital angle at T = 0, rad */
+  double sidereal_day_s;   /* rotation period (86164 s in the workloads) */
+  double gmst0_rad;        /* sidereal angle of Greenwich at T = 0 */
+} fstat_ephemeris;
+
+/* One data segment.  The observation time n dt must be a whole number of
+ * sidereal days (the assumption under which <ab> = 0 and Eq. (OS) holds,
+ * Sec. III A). */
+typedef struct {
+  const double *x;          /* host [n]: real narrow-band samples */
+  int64_t n;                /* samples, >= 16 */
+  double dt;                /* sampling interval, s */
+  int32_t n_sidereal_days;  /* n dt / sidereal_day_s, >= 1 */
+  double t0;                /* ephemeris time of the first sample, s */
+  const uint8_t *mask;      /* host [n] or NULL: 0 marks a gap (sample ignored) */
+  double f_ref_hz;          /* lower band edge */
+  double sigma2;            /* noise variance per sample; <= 0: estimated from the
+                               data outside gaps (unbiased sample variance) */
+  int64_t nfft;             /* FFT length: power of two, n <= nfft <= 2^22;
+                               0 = smallest power of two >= 2n */
+} fstat_segment;
+
+typedef struct {
+  int32_t interp;    /* FSTAT_NEAREST / FSTAT_LINEAR_UP2 / FSTAT_CUBIC_UP2 */
+  int32_t prec;      /* FSTAT_FP32 / FSTAT_FP64 */
+  int32_t device;    /* HIP device ordinal */
+  int32_t max_batch; /* nodes per FFT batch; 0 = library default */
+} fstat_options;
+
+typedef struct fstat_plan_s *fstat_plan_t;
+
+/* Create a plan: copies the segments to the device and does the
+ * node-independent preparation (gap mask, noise variance, 2x upsampling and
+ * spline for the two-step interpolations).  Synchronous.  On success *out
+ * receives the plan; release it with fstat_destroy. */
+fstat_status fstat_plan(const fstat_segment *segs, int32_t nseg, const fstat_detector *det,
+                        const fstat_ephemeris *eph, const fstat_options *opt, fstat_plan_t *out);
+
+/* A grid node: sky position, spindown (Hz/s), segment index. */
+typedef struct {
+  double alpha;   /* right ascension, rad */
+  double delta;   /* declination, rad */
+  double fdot;    /* first spindown, Hz/s */
+  int32_t seg;    /* segment of the plan */
+  int32_t pad;
+} fstat_node;
+
+/* A threshold crossing (output mode FSTAT_OUT_CROSSINGS). */
+typedef struct {
+  int64_t node;   /* index into the node array of the call */
+  int64_t k;      /* Fourier bin */
+  double F;
+} fstat_crossing;
+
+/* Output descriptor of fstat_grid.  The element type of F and Fmax is float
+ * for an FSTAT_FP32 plan and double for an FSTAT_FP64 plan. */
+typedef struct {
+  int32_t mode;             /* FSTAT_OUT_MAP / _MAX / _CROSSINGS */
+  int32_t pad;
+  int64_t k_lo, k_hi;       /* bins 0 <= k_lo < k_hi <= nfft/2 of every node's segment */
+  double threshold;         /* mode CROSSINGS: report F > threshold */
+  void *F;                  /* device [n_nodes][k_hi - k_lo] (mode MAP) */
+  void *Fmax;               /* device [n_nodes] (mode MAX) */
+  int64_t *kmax;            /* device [n_nodes] (mode MAX); ties go to the lowest bin */
+  fstat_crossing *crossings;      /* device [max_crossings] (mode CROSSINGS), unordered */
+  unsigned long long *n_crossings;/* device [1]: number of crossings found (may exceed
+                                     max_crossings; records beyond it are dropped) */
+  int64_t max_crossings;
+} fstat_out;
+
+/* F-statistic of Eq. (OS) on the Fourier bins of every node (Sec. VI):
+ *   F_k = (B |S_a,k|^2 + A |S_b,k|^2 - 2 C Re(S_a,k S_b,k*)) / (sigma^2 (A B - C^2)),
+ *   S_a,k = sum_j x(t_j) a(t_j) e^{-i phi_s(t_j)} e^{-2 pi i j k / nfft},
+ * with t_j the detector time of barycentric time t_b0 + j dt, A, B, C the sums
+ * of a^2, b^2, ab over the detector samples outside gaps (C vanishes for
+ * whole sidereal days without gaps, which gives Eq. OS exactly).
+ * nodes: host [n_nodes].  The F values are written on hip_stream; the call
+ * returns once the work is enqueued. */
+fstat_status fstat_grid(fstat_plan_t p, const fstat_node *nodes, int64_t n_nodes, const fstat_out *out,
+                        void *hip_stream);
+
+/* F at continuous parameters by the same resampling method (the sum over the
+ * barycentric grid with e^{-2 pi i f j dt} in place of the FFT kernel), for
+ * candidate refinement off the grid.  All FP64.
+ *   params: device [n][4] = (f band-relative Hz, fdot Hz/s, alpha rad, delta rad)
+ *   seg:    device [n] segment indices, or NULL for segment 0
+ *   F:      device [n]
+ *   state:  device [n][FSTAT_STATE] or NULL: what fstat_adjoint needs
+ *           (S_a, S_b, A, B, C) */
+#define FSTAT_STATE 8
+fstat_status fstat_eval(fstat_plan_t p, const double *params, const int32_t *seg, int64_t n, double *F,
+                        double *state, void *hip_stream);
+
+/* Reverse-mode (adjoint) pass of fstat_eval: dparams[i][:] = gF[i] * dF_i/d(f, fdot,
+ * alpha, delta), recomputing the resampled series rather than storing it.
+ * Differentiates through t_b0(alpha, delta), the implicit relation
+ * t_j + phi_m(t_j) = t_b0 + j dt, the interpolant (zero for FSTAT_NEAREST),
+ * a(t_j), b(t_j), the phase, and A, B, C.
+ *   state: device [n][FSTAT_STATE] from fstat_eval with the same params
+ *   gF:    device [n] upstream gradient, or NULL for ones
+ *   dparams: device [n][4] */
+fstat_status fstat_adjoint(fstat_plan_t p, const double *params, const int32_t *seg, int64_t n,
+                           const double *state, const double *gF, double *dparams, void *hip_stream);
+
+/* Convenience: F and (if dF != NULL) dF/d(f, fdot, alpha, delta), device [n] and [n][4]. */
+fstat_status fstat_grad(fstat_plan_t p, const double *params, const int32_t *seg, int64_t n, double *F,
+                        double *dF, void *hip_stream);
+
+/* Plan facts.  Host outputs; any pointer may be NULL. */
+fstat_status fstat_plan_info(fstat_plan_t p, int32_t seg, int64_t *n, int64_t *nfft, double *sigma2,
+                             int32_t *fft_R, int32_t *fft_C);
+
+/* Diagnostic: the demodulated, resampled, a/b-weighted series z_a, z_b of one
+ * node (the input of the FFTs, natural order), as FP64 device [n][4] =
+ * (Re z_a, Im z_a, Re z_b, Im z_b), computed in the plan's precision. */
+fstat_status fstat_demod_series(fstat_plan_t p, const fstat_node *node, double *out, void *hip_stream);
+
+/* Kernel timing (a tracing aid, off by default).  While enabled, every kernel
+ * launch of fstat_grid is bracketed by two HIP events on the caller's stream.
+ * fstat_profile(p, 1) enables and resets the counters, fstat_profile(p, 0)
+ * disables.  fstat_profile_read synchronises the device and returns, for one
+ * kernel kind, the number of launches, their summed duration in milliseconds
+ * and their summed algorithmic HBM bytes (the bytes the launch must move:
+ *   FSTAT_K_PASS1: 4 complex values of the working precision per FFT bin
+ *                  written (the a- and b-spectra between the passes), plus the
+ *                  per-sample sky record read (4 reals per sample);
+ *   FSTAT_K_PASS2: the same spectra read back, plus one real per output bin
+ *                  written;
+ *   FSTAT_K_SKY:   the sky records written, 4 reals per sample.)
+ * Any output pointer may be NULL. */
+#define FSTAT_K_SKY 0
+#define FSTAT_K_PASS1 1
+#define FSTAT_K_PASS2 2
+#define FSTAT_K_OTHER 3
+fstat_status fstat_profile(fstat_plan_t p, int32_t enable);
+fstat_status fstat_profile_read(fstat_plan_t p, int32_t kind, int64_t *launches, double *ms, double *bytes);
+
+void fstat_destroy(fstat_plan_t p);
+const char *fstat_strerror(fstat_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FSTAT_H */

@@ -22,7 +22,9 @@ R-band   The data are real, narrow-band, heterodyned: band-relative frequency f
          enters the Roemer term of Eq. (pha3).
 R-grid   SSB time grid: t_b0 = t_b(0) = phi_m(0), t_b_j = t_b0 + j dt,
          j = 0..N-1 (the same number of points as the data, Sec. VI A).
-         The resampled value is 0 where t(t_b) falls outside [0, (N-1) dt].
+         The resampled value is 0 where t(t_b) falls outside [0, (N-1) dt],
+         with a margin of 1e-6 samples (clamped), because t_0 = 0 exactly and
+         its rounding must not decide whether the first sample counts.
 R-interp Only x is interpolated; a(t), b(t) and the demodulation phase are
          evaluated exactly at t(t_b_j) (Eq. ia read literally).  Nearest
          neighbour takes x[floor(u + 1/2)], u = t/dt.  The two-step method
@@ -158,12 +160,20 @@ def _upsampled(seg: Segment, mode):
     return seg._cache[key]
 
 
+SPAN_EPS = 1e-6  # samples
+
+
 def interpolate(seg: Segment, u, mode):
-    """x at fractional sample positions u (0 outside [0, N-1]), and dx/du."""
+    """x at fractional sample positions u (0 outside [0, N-1]), and dx/du.
+
+    The first barycentric sample maps exactly onto the first data sample
+    (t_b0 = phi_m(0) gives t_0 = 0), so the span test must not depend on the
+    last bit of t: positions within SPAN_EPS samples of the span count as
+    inside and are clamped onto it."""
     u = np.asarray(u, dtype=np.float64)
     n = seg.n
-    valid = (u >= 0.0) & (u <= n - 1)
-    uu = np.where(valid, u, 0.0)
+    valid = (u >= -SPAN_EPS) & (u <= n - 1 + SPAN_EPS)
+    uu = np.where(valid, np.clip(u, 0.0, n - 1.0), 0.0)
     xr = np.zeros_like(u)
     dxdu = np.zeros_like(u)
     if mode == NEAREST:
@@ -203,18 +213,27 @@ def resampled(seg: Segment, alpha, delta, det, eph, mode):
     return dict(tb0=tb0, t=t, u=u, xr=xr, dxdu=dxdu, a=a, b=b, pm=pm)
 
 
-def demod_cycles(t, pm, f_ref, fdot):
-    """Frequency-independent part of the phase on the resampled grid, cycles:
-    f_ref phi_m + fdot (t^2/2 + phi_m t)  (Eq. phas plus the f_ref part of
-    omega_0 phi_m that the band-relative FFT does not absorb)."""
-    return f_ref * pm + fdot * (0.5 * t * t + pm * t)
+def demod_cycles(t, T0, alpha, delta, f_ref, fdot, det, eph):
+    """Frequency-independent part of the phase on the resampled grid, turns,
+    reduced to [-1/2, 1/2]:
+        f_ref (phi_m(t) - phi_m(0)) + fdot (t^2/2 + phi_m(t) t)
+    (Eq. phas plus the f_ref part of omega_0 phi_m that the band-relative FFT
+    does not absorb; the constant f_ref phi_m(0) is a phase common to S_a and
+    S_b and is left out, reading R-f0).  Evaluated in extended precision: the
+    f_ref phi_m term alone reaches ~2e5 turns."""
+    L = np.longdouble
+    tl = np.asarray(t, dtype=L)
+    pm = model.roemer_delay_ext(L(T0) + tl, alpha, delta, det, eph)
+    pm0 = model.roemer_delay_ext(L(T0), alpha, delta, det, eph)
+    cyc = L(f_ref) * (pm - pm0) + L(fdot) * (tl * tl / 2 + pm * tl)
+    return (cyc - np.round(cyc)).astype(np.float64)
 
 
 def demodulated(seg: Segment, fdot, alpha, delta, det, eph, mode):
     """z_a, z_b on the SSB grid: x(t(t_b)) a(t(t_b)) e^{-i phi_s(t(t_b))}."""
     r = resampled(seg, alpha, delta, det, eph, mode)
-    cyc = demod_cycles(r["t"], r["pm"], seg.f_ref, fdot)
-    e = np.exp(-2j * math.pi * (cyc - np.round(cyc)))
+    cyc = demod_cycles(r["t"], seg.t0, alpha, delta, seg.f_ref, fdot, det, eph)
+    e = np.exp(-2j * math.pi * cyc)
     return r["xr"] * r["a"] * e, r["xr"] * r["b"] * e
 
 
@@ -338,7 +357,7 @@ def fstat_continuous(seg: Segment, params, det, eph, mode, grad=False):
     xr, dxdu = interpolate(seg, t / dt, mode)
     pm, pm_al, pm_de, pm_T = _roemer_partials(T, alpha, delta, det, eph)
     a, b, a_x, b_x, a_d, b_d = _ab_partials(T, alpha, delta, det, eph)
-    cyc = demod_cycles(t, pm, seg.f_ref, fdot) + f * j * dt
+    cyc = demod_cycles(t, seg.t0, alpha, delta, seg.f_ref, fdot, det, eph) + f * j * dt
     e = np.exp(-2j * math.pi * (cyc - np.round(cyc)))
     Sa = np.sum(xr * a * e)
     Sb = np.sum(xr * b * e)

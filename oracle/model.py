@@ -99,6 +99,25 @@ def roemer_delay(T, alpha, delta, det: Detector, eph: Ephemeris):
     return dot / C_LIGHT
 
 
+def roemer_delay_ext(T, alpha, delta, det: Detector, eph: Ephemeris):
+    """The same scalar product in extended precision (numpy longdouble, a
+    64-bit mantissa on x86-64).  Used where the delay is multiplied by f_ref:
+    f_ref phi_m reaches ~2e5 turns, where FP64 rounding alone would leave
+    ~1e-11 turn of error."""
+    L = np.longdouble
+    T = np.asarray(T, dtype=L)
+    two_pi = 2 * L(np.pi)
+    ang = L(eph.orbit_omega) * T + L(eph.orbit_phase0)
+    xes, yes = L(eph.orbit_radius) * np.cos(ang), L(eph.orbit_radius) * np.sin(ang)
+    th = L(eph.gmst0) + L(det.lon) + two_pi * T / L(eph.sidereal_day)
+    rc = L(det.radius) * np.cos(L(det.lat))
+    xe, ye, ze = rc * np.cos(th), rc * np.sin(th), L(det.radius) * np.sin(L(det.lat))
+    a, d, e = L(alpha), L(delta), L(eph.obliquity)
+    ca, sa, cd, sd, ce, se = np.cos(a), np.sin(a), np.cos(d), np.sin(d), np.cos(e), np.sin(e)
+    dot = ca * cd * (xes + xe) + (sa * cd * ce + sd * se) * yes + sa * cd * ye + sd * ze
+    return dot / L(C_LIGHT)
+
+
 # --------------------------------------------------------------------------
 # Amplitude modulation (Sec. II, Eq. patt)
 # --------------------------------------------------------------------------

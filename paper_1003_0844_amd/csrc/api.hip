@@ -1,0 +1,657 @@
+// The C ABI of include/fstat.h: validation, plan state, workspace and the
+// launch sequence of a grid call.  Host code only; every arithmetic step of the
+// method runs in the kernels of sky.hip, grid.hip, prep.hip and grad.hip.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/fstat.h"
+#include "internal.h"
+
+namespace {
+
+constexpr double C_LIGHT = 299792458.0;
+constexpr double TWO_PI = 6.283185307179586476925286766559;
+
+struct SegPlan {
+  SegDev dev{};
+  int B2 = 0;
+  void* twC = nullptr;
+  void* twR = nullptr;
+  void* twlo = nullptr;
+  void* twhi = nullptr;
+  double* x = nullptr;
+  float* xf = nullptr;
+  double* y = nullptr;
+  float* yf = nullptr;
+  double* M = nullptr;
+  float* Mf = nullptr;
+  uint8_t* mask = nullptr;
+};
+
+struct ProfPair {
+  hipEvent_t a, b;
+  int kind;
+  double bytes;
+};
+struct ProfKind {
+  int64_t launches = 0;
+  double ms = 0.0;
+  double bytes = 0.0;
+};
+struct Prof {
+  bool on = false;
+  std::vector<ProfPair> pending, pool;
+  ProfKind kinds[4];
+};
+
+}  // namespace
+
+struct fstat_plan_s {
+  Prof prof;
+  int device = 0;
+  int interp = 1;
+  int prec = 0;
+  int max_batch = 0;
+  std::vector<SegPlan> segs;
+  SegDev* d_segs = nullptr;
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  void* pinned = nullptr;
+  size_t pinned_bytes = 0;
+  hipEvent_t staged = nullptr;
+  bool staged_pending = false;
+};
+
+namespace {
+
+fstat_status from_hip(hipError_t e) {
+  if (e == hipSuccess) return FSTAT_OK;
+  if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return FSTAT_ENOMEM;
+  return FSTAT_EDEVICE;
+}
+
+#define HIP_TRY(expr)                               \
+  do {                                              \
+    hipError_t e_ = (expr);                         \
+    if (e_ != hipSuccess) return from_hip(e_);      \
+  } while (0)
+
+bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+int64_t next_pow2(int64_t v) {
+  int64_t p = 1;
+  while (p < v) p <<= 1;
+  return p;
+}
+double frac_turns(double v) {
+  double f = v - std::floor(v);
+  return f >= 1.0 ? 0.0 : f;
+}
+
+// nfft = R * C for the two FFT passes
+void choose_split(int prec, int64_t nfft, int& R, int& C) {
+  int64_t c = prec == 0 ? 4096 : 2048;
+  if (nfft / 16 < c) c = nfft / 16;
+  if (nfft / c > 1024) c = nfft / 1024;
+  C = (int)c;
+  R = (int)(nfft / c);
+}
+
+size_t elem_real(int prec) { return prec == 0 ? 4 : 8; }
+
+void free_seg(SegPlan& s) {
+  void* ptrs[] = {s.twC, s.twR, s.twlo, s.twhi, s.x, s.xf, s.y, s.yf, s.M, s.Mf, s.mask};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  s = SegPlan{};
+}
+
+void destroy_plan(fstat_plan_s* p) {
+  if (!p) return;
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  (void)hipSetDevice(p->device);
+  (void)hipDeviceSynchronize();
+  for (auto& s : p->segs) free_seg(s);
+  if (p->d_segs) (void)hipFree(p->d_segs);
+  if (p->ws) (void)hipFree(p->ws);
+  if (p->pinned) (void)hipHostFree(p->pinned);
+  if (p->staged) (void)hipEventDestroy(p->staged);
+  for (auto* v : {&p->prof.pending, &p->prof.pool})
+    for (auto& pr : *v) {
+      (void)hipEventDestroy(pr.a);
+      (void)hipEventDestroy(pr.b);
+    }
+  (void)hipSetDevice(cur);
+  delete p;
+}
+
+// Restores the caller's current device on scope exit.
+struct DeviceGuard {
+  int prev = 0;
+  bool ok = false;
+  explicit DeviceGuard(int dev) {
+    ok = hipGetDevice(&prev) == hipSuccess && hipSetDevice(dev) == hipSuccess;
+  }
+  ~DeviceGuard() {
+    if (ok) (void)hipSetDevice(prev);
+  }
+};
+
+fstat_status validate_segment(const fstat_segment& s, const fstat_ephemeris& eph, int prec) {
+  if (!s.x || s.n <= 0 || !(s.dt > 0.0) || !std::isfinite(s.dt) || s.n_sidereal_days <= 0 ||
+      !std::isfinite(s.f_ref_hz) || !std::isfinite(s.t0) || !std::isfinite(s.sigma2))
+    return FSTAT_EINVAL;
+  if (s.n < 16) return FSTAT_EUNSUPPORTED;
+  if (std::fabs((double)s.n * s.dt - (double)s.n_sidereal_days * eph.sidereal_day_s) > 0.5 * s.dt)
+    return FSTAT_ENOTINTDAYS;
+  const int64_t nfft = s.nfft ? s.nfft : next_pow2(2 * s.n);
+  if (nfft < 0) return FSTAT_EINVAL;
+  if (!is_pow2(nfft) || nfft < s.n || nfft < (1 << 10) || nfft > (1 << 22)) return FSTAT_EUNSUPPORTED;
+  for (int64_t i = 0; i < s.n; ++i)
+    if (!std::isfinite(s.x[i])) return FSTAT_EINVAL;
+  (void)prec;
+  return FSTAT_OK;
+}
+
+fstat_status build_segment(const fstat_segment& s, const fstat_detector& det, const fstat_ephemeris& eph, int prec,
+                           int interp, SegPlan& sp) {
+  const int64_t n = s.n;
+  const int64_t nfft = s.nfft ? s.nfft : next_pow2(2 * n);
+  SegDev& d = sp.dev;
+  // geometry constants (turns for the angles, light-seconds for distances)
+  d.geo.orb_r = eph.orbit_radius_m / C_LIGHT;
+  d.geo.orb_rate_c = eph.orbit_omega / TWO_PI;
+  d.geo.orb_c0 = frac_turns(eph.orbit_phase0 / TWO_PI + s.t0 * d.geo.orb_rate_c);
+  d.geo.site_rc = det.radius_m * std::cos(det.lat_rad) / C_LIGHT;
+  d.geo.site_rz = det.radius_m * std::sin(det.lat_rad) / C_LIGHT;
+  d.geo.sid_rate_c = 1.0 / eph.sidereal_day_s;
+  d.geo.sid_c0 = frac_turns((eph.gmst0_rad + det.lon_rad) / TWO_PI + s.t0 / eph.sidereal_day_s);
+  d.geo.cth0 = std::cos(TWO_PI * d.geo.sid_c0);
+  d.geo.sth0 = std::sin(TWO_PI * d.geo.sid_c0);
+  d.geo.ceps = std::cos(eph.obliquity_rad);
+  d.geo.seps = std::sin(eph.obliquity_rad);
+  d.geo.s2g = std::sin(2.0 * det.gamma_rad);
+  d.geo.c2g = std::cos(2.0 * det.gamma_rad);
+  d.geo.sl = std::sin(det.lat_rad);
+  d.geo.cl = std::cos(det.lat_rad);
+  d.geo.s2l = std::sin(2.0 * det.lat_rad);
+  d.geo.c2l = std::cos(2.0 * det.lat_rad);
+  d.n = n;
+  d.dt = s.dt;
+  d.f_ref = s.f_ref_hz;
+  d.nfft = nfft;
+  int R, C;
+  choose_split(prec, nfft, R, C);
+  d.R = R;
+  d.C = C;
+  d.Ceff = (int)((n + R - 1) / R);
+  d.interp = interp;
+  sp.B2 = fsk::pass2_b2(prec, R);
+
+  const size_t er = elem_real(prec);
+  double* xraw = nullptr;
+  void* work = nullptr;
+  double* dvar = nullptr;
+  fstat_status rc = FSTAT_OK;
+  auto fail = [&](hipError_t e) {
+    rc = from_hip(e);
+    return rc;
+  };
+  hipError_t e = hipSuccess;
+  do {
+    if ((e = hipMalloc(&xraw, n * sizeof(double))) != hipSuccess) break;
+    if ((e = hipMalloc(&sp.x, n * sizeof(double))) != hipSuccess) break;
+    if ((e = hipMalloc(&sp.xf, n * sizeof(float))) != hipSuccess) break;
+    if ((e = hipMemcpy(xraw, s.x, n * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess) break;
+    if (s.mask) {
+      if ((e = hipMalloc(&sp.mask, n)) != hipSuccess) break;
+      if ((e = hipMemcpy(sp.mask, s.mask, n, hipMemcpyHostToDevice)) != hipSuccess) break;
+    }
+    if ((e = fsk::prep_mask(xraw, sp.mask, n, sp.x, sp.xf, nullptr)) != hipSuccess) break;
+    double sigma2 = s.sigma2;
+    if (!(sigma2 > 0.0)) {
+      if ((e = hipMalloc(&dvar, sizeof(double))) != hipSuccess) break;
+      if ((e = fsk::prep_variance(xraw, sp.mask, n, dvar, nullptr)) != hipSuccess) break;
+      if ((e = hipMemcpy(&sigma2, dvar, sizeof(double), hipMemcpyDeviceToHost)) != hipSuccess) break;
+      if (!(sigma2 > 0.0) || !std::isfinite(sigma2)) {
+        rc = FSTAT_EINVAL;
+        break;
+      }
+    }
+    d.sigma2 = sigma2;
+    if (interp != FSTAT_NEAREST) {
+      if ((e = hipMalloc(&sp.y, 2 * n * sizeof(double))) != hipSuccess) break;
+      if ((e = hipMalloc(&sp.yf, 2 * n * sizeof(float))) != hipSuccess) break;
+      if (interp == FSTAT_CUBIC_UP2) {
+        if ((e = hipMalloc(&sp.M, 2 * n * sizeof(double))) != hipSuccess) break;
+        if ((e = hipMalloc(&sp.Mf, 2 * n * sizeof(float))) != hipSuccess) break;
+      }
+      if ((e = hipMalloc(&work, fsk::prep_work_bytes(n))) != hipSuccess) break;
+      if ((e = fsk::prep_upsample(sp.x, n, interp, sp.y, sp.yf, sp.M, sp.Mf, work, nullptr)) != hipSuccess) break;
+    }
+    // twiddle tables in the working precision
+    const int64_t nlo = nfft < 4096 ? nfft : 4096;
+    const int64_t nhi = nfft / 4096 > 1 ? nfft / 4096 : 1;
+    if ((e = hipMalloc(&sp.twC, C * 2 * er)) != hipSuccess) break;
+    if ((e = hipMalloc(&sp.twR, R * 2 * er)) != hipSuccess) break;
+    if ((e = hipMalloc(&sp.twlo, 4096 * 2 * er)) != hipSuccess) break;
+    if ((e = hipMalloc(&sp.twhi, nhi * 2 * er)) != hipSuccess) break;
+    if ((e = fsk::make_twiddles(prec, C, C, 1, sp.twC, nullptr)) != hipSuccess) break;
+    if ((e = fsk::make_twiddles(prec, R, R, 1, sp.twR, nullptr)) != hipSuccess) break;
+    if ((e = fsk::make_twiddles(prec, nfft, nlo, 1, sp.twlo, nullptr)) != hipSuccess) break;
+    if ((e = fsk::make_twiddles(prec, nfft, nhi, 4096, sp.twhi, nullptr)) != hipSuccess) break;
+    if ((e = hipDeviceSynchronize()) != hipSuccess) break;
+  } while (0);
+  if (e != hipSuccess) fail(e);
+  (void)hipDeviceSynchronize();
+  if (xraw) (void)hipFree(xraw);
+  if (work) (void)hipFree(work);
+  if (dvar) (void)hipFree(dvar);
+  d.x = sp.x;
+  d.xf = sp.xf;
+  d.y = sp.y;
+  d.yf = sp.yf;
+  d.M = sp.M;
+  d.Mf = sp.Mf;
+  d.mask = sp.mask;
+  return rc;
+}
+
+// ---------------------------------------------------------------------------
+// workspace
+// ---------------------------------------------------------------------------
+fstat_status ensure_ws(fstat_plan_s* p, size_t bytes) {
+  if (p->ws_bytes >= bytes) return FSTAT_OK;
+  HIP_TRY(hipDeviceSynchronize());
+  if (p->ws) (void)hipFree(p->ws);
+  p->ws = nullptr;
+  p->ws_bytes = 0;
+  HIP_TRY(hipMalloc(&p->ws, bytes));
+  p->ws_bytes = bytes;
+  return FSTAT_OK;
+}
+
+fstat_status ensure_pinned(fstat_plan_s* p, size_t bytes) {
+  if (p->staged_pending) {
+    HIP_TRY(hipEventSynchronize(p->staged));
+    p->staged_pending = false;
+  }
+  if (p->pinned_bytes >= bytes) return FSTAT_OK;
+  if (p->pinned) (void)hipHostFree(p->pinned);
+  p->pinned = nullptr;
+  p->pinned_bytes = 0;
+  HIP_TRY(hipHostMalloc(&p->pinned, bytes, hipHostMallocDefault));
+  p->pinned_bytes = bytes;
+  return FSTAT_OK;
+}
+
+size_t align_up(size_t v, size_t a = 256) { return (v + a - 1) / a * a; }
+
+// Launch through f(); when profiling is on, bracket it with two events.
+template <class F>
+hipError_t timed(fstat_plan_s* p, int kind, double bytes, hipStream_t st, F&& f) {
+  if (!p->prof.on) return f();
+  ProfPair pr{};
+  if (!p->prof.pool.empty()) {
+    pr = p->prof.pool.back();
+    p->prof.pool.pop_back();
+  } else {
+    hipError_t e = hipEventCreate(&pr.a);
+    if (e == hipSuccess) e = hipEventCreate(&pr.b);
+    if (e != hipSuccess) return e;
+  }
+  pr.kind = kind;
+  pr.bytes = bytes;
+  hipError_t e = hipEventRecord(pr.a, st);
+  if (e == hipSuccess) e = f();
+  if (e == hipSuccess) e = hipEventRecord(pr.b, st);
+  if (e != hipSuccess) {
+    p->prof.pool.push_back(pr);
+    return e;
+  }
+  p->prof.pending.push_back(pr);
+  return hipSuccess;
+}
+
+struct Carve {
+  char* base;
+  size_t off = 0;
+  template <typename T>
+  T* take(size_t count) {
+    T* r = (T*)(base + off);
+    off = align_up(off + count * sizeof(T));
+    return r;
+  }
+};
+
+// one unit of work: a batch of sky positions of one segment, and its nodes
+struct SkyBatch {
+  int seg;
+  int sky0, nsky;    // into the call's sky list (alpha, delta pairs)
+  int node0, nnode;  // into the call's NodeDev list (sky = index within the batch)
+};
+
+}  // namespace
+
+// ===========================================================================
+extern "C" {
+
+const char* fstat_strerror(fstat_status s) {
+  switch (s) {
+    case FSTAT_OK: return "ok";
+    case FSTAT_EINVAL: return "invalid argument";
+    case FSTAT_ENOTINTDAYS: return "observation time is not a whole number of sidereal days";
+    case FSTAT_ENOMEM: return "out of memory";
+    case FSTAT_EDEVICE: return "HIP device error";
+    case FSTAT_EUNSUPPORTED: return "unsupported size";
+    default: return "unknown status";
+  }
+}
+
+fstat_status fstat_plan(const fstat_segment* segs, int32_t nseg, const fstat_detector* det,
+                        const fstat_ephemeris* eph, const fstat_options* opt, fstat_plan_t* out) {
+  if (!segs || nseg <= 0 || !det || !eph || !opt || !out) return FSTAT_EINVAL;
+  if (opt->interp < 0 || opt->interp > 2 || opt->prec < 0 || opt->prec > 1 || opt->max_batch < 0)
+    return FSTAT_EINVAL;
+  if (!(eph->sidereal_day_s > 0.0) || !std::isfinite(eph->orbit_radius_m) || !std::isfinite(eph->orbit_omega) ||
+      !std::isfinite(det->radius_m) || !std::isfinite(det->lat_rad))
+    return FSTAT_EINVAL;
+  for (int i = 0; i < nseg; ++i) {
+    fstat_status v = validate_segment(segs[i], *eph, opt->prec);
+    if (v != FSTAT_OK) return v;
+  }
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return FSTAT_EDEVICE;
+  if (opt->device < 0 || opt->device >= ndev) return FSTAT_EINVAL;
+  DeviceGuard guard(opt->device);
+  if (!guard.ok) return FSTAT_EDEVICE;
+
+  fstat_plan_s* p = new (std::nothrow) fstat_plan_s();
+  if (!p) return FSTAT_ENOMEM;
+  p->device = opt->device;
+  p->interp = opt->interp;
+  p->prec = opt->prec;
+  p->max_batch = opt->max_batch;
+  p->segs.resize(nseg);
+  for (int i = 0; i < nseg; ++i) {
+    fstat_status rc = build_segment(segs[i], *det, *eph, opt->prec, opt->interp, p->segs[i]);
+    if (rc != FSTAT_OK) {
+      destroy_plan(p);
+      return rc;
+    }
+  }
+  std::vector<SegDev> hs(nseg);
+  for (int i = 0; i < nseg; ++i) hs[i] = p->segs[i].dev;
+  hipError_t e = hipMalloc(&p->d_segs, nseg * sizeof(SegDev));
+  if (e == hipSuccess) e = hipMemcpy(p->d_segs, hs.data(), nseg * sizeof(SegDev), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&p->staged, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    destroy_plan(p);
+    return from_hip(e);
+  }
+  *out = p;
+  return FSTAT_OK;
+}
+
+void fstat_destroy(fstat_plan_t p) { destroy_plan(p); }
+
+fstat_status fstat_plan_info(fstat_plan_t p, int32_t seg, int64_t* n, int64_t* nfft, double* sigma2, int32_t* R,
+                             int32_t* C) {
+  if (!p || seg < 0 || seg >= (int32_t)p->segs.size()) return FSTAT_EINVAL;
+  const SegDev& d = p->segs[seg].dev;
+  if (n) *n = d.n;
+  if (nfft) *nfft = d.nfft;
+  if (sigma2) *sigma2 = d.sigma2;
+  if (R) *R = d.R;
+  if (C) *C = d.C;
+  return FSTAT_OK;
+}
+
+fstat_status fstat_grid(fstat_plan_t p, const fstat_node* nodes, int64_t n_nodes, const fstat_out* out,
+                        void* hip_stream) {
+  if (!p || !nodes || n_nodes <= 0 || !out) return FSTAT_EINVAL;
+  if (n_nodes > (int64_t)INT32_MAX) return FSTAT_EUNSUPPORTED;
+  if (out->mode < 0 || out->mode > 2) return FSTAT_EINVAL;
+  if (out->k_lo < 0 || out->k_hi <= out->k_lo) return FSTAT_EINVAL;
+  if (out->mode == 0 && !out->F) return FSTAT_EINVAL;
+  if (out->mode == 1 && (!out->Fmax || !out->kmax)) return FSTAT_EINVAL;
+  if (out->mode == 2 && (!out->n_crossings || (out->max_crossings > 0 && !out->crossings) || out->max_crossings < 0))
+    return FSTAT_EINVAL;
+  const int nseg = (int)p->segs.size();
+  for (int64_t i = 0; i < n_nodes; ++i) {
+    const fstat_node& nd = nodes[i];
+    if (nd.seg < 0 || nd.seg >= nseg || !std::isfinite(nd.alpha) || !std::isfinite(nd.delta) ||
+        !std::isfinite(nd.fdot))
+      return FSTAT_EINVAL;
+    if (out->k_hi > p->segs[nd.seg].dev.nfft / 2) return FSTAT_EINVAL;
+  }
+  DeviceGuard guard(p->device);
+  if (!guard.ok) return FSTAT_EDEVICE;
+  hipStream_t st = (hipStream_t)hip_stream;
+  const int prec = p->prec;
+
+  // ---- group nodes: by segment, then by sky position ----
+  std::vector<int64_t> order(n_nodes);
+  for (int64_t i = 0; i < n_nodes; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
+    const fstat_node &x = nodes[a], &y = nodes[b];
+    if (x.seg != y.seg) return x.seg < y.seg;
+    if (x.alpha != y.alpha) return x.alpha < y.alpha;
+    return x.delta < y.delta;
+  });
+  std::vector<double> sky_ad;      // (alpha, delta) per sky of the call
+  std::vector<NodeDev> ndev;       // per node, grouped by batch
+  std::vector<SkyBatch> batches;
+  // batch sizing per segment
+  size_t need_ws = 0;
+  {
+    int64_t i = 0;
+    while (i < n_nodes) {
+      const int sg = nodes[order[i]].seg;
+      const SegDev& d = p->segs[sg].dev;
+      const size_t quad_bytes = (size_t)d.R * d.Ceff * 4 * elem_real(prec);
+      int sky_cap = (int)std::max<size_t>(1, std::min<size_t>(64, ((size_t)1 << 30) / quad_bytes));
+      SkyBatch b{sg, (int)(sky_ad.size() / 2), 0, (int)ndev.size(), 0};
+      while (i < n_nodes && nodes[order[i]].seg == sg) {
+        const fstat_node& nd = nodes[order[i]];
+        const bool new_sky = b.nsky == 0 || sky_ad[sky_ad.size() - 2] != nd.alpha || sky_ad.back() != nd.delta;
+        if (new_sky) {
+          if (b.nsky == sky_cap) {
+            batches.push_back(b);
+            b = SkyBatch{sg, (int)(sky_ad.size() / 2), 0, (int)ndev.size(), 0};
+          }
+          sky_ad.push_back(nd.alpha);
+          sky_ad.push_back(nd.delta);
+          ++b.nsky;
+        }
+        ndev.push_back(NodeDev{nd.fdot, b.nsky - 1, (int32_t)order[i]});
+        ++b.nnode;
+        ++i;
+      }
+      batches.push_back(b);
+    }
+  }
+  // workspace: descriptors + per-batch sky data + spill + partials
+  int node_cap = p->max_batch > 0 ? p->max_batch : (prec == 0 ? 16 : 4);
+  size_t max_quads = 0, max_spill = 0, max_part = 0, max_abc = 0;
+  int max_sky = 0;
+  for (const auto& b : batches) {
+    const SegPlan& sp = p->segs[b.seg];
+    const SegDev& d = sp.dev;
+    max_quads = std::max(max_quads, (size_t)b.nsky * d.R * d.Ceff * 4 * elem_real(prec));
+    max_spill = std::max(max_spill, (size_t)node_cap * d.nfft * 4 * elem_real(prec));
+    max_part = std::max(max_part, (size_t)node_cap * (d.C / sp.B2) * sizeof(MaxPartial));
+    max_abc = std::max(max_abc, (size_t)b.nsky * fsk::sky_prep_blocks(d) * 3 * sizeof(double));
+    max_sky = std::max(max_sky, b.nsky);
+  }
+  const size_t desc_bytes = align_up(sky_ad.size() * sizeof(double)) + align_up(ndev.size() * sizeof(NodeDev));
+  need_ws = desc_bytes + align_up(max_quads) + align_up(max_spill) + align_up(max_part) + align_up(max_abc) +
+            align_up(max_sky * sizeof(SkyConst)) + align_up(max_sky * sizeof(SkyCoef)) + 4096;
+  fstat_status rc = ensure_ws(p, need_ws);
+  if (rc != FSTAT_OK) return rc;
+  rc = ensure_pinned(p, desc_bytes);
+  if (rc != FSTAT_OK) return rc;
+  Carve cv{(char*)p->ws};
+  double* d_ad = cv.take<double>(sky_ad.size());
+  NodeDev* d_nodes = cv.take<NodeDev>(ndev.size());
+  void* d_quads = cv.take<char>(max_quads);
+  void* d_spill = cv.take<char>(max_spill);
+  MaxPartial* d_part = cv.take<MaxPartial>(max_part / sizeof(MaxPartial) + 1);
+  double* d_abc = cv.take<double>(max_abc / sizeof(double) + 1);
+  SkyConst* d_sky = cv.take<SkyConst>(max_sky);
+  SkyCoef* d_coef = cv.take<SkyCoef>(max_sky);
+  // stage descriptors
+  char* hp = (char*)p->pinned;
+  std::memcpy(hp, sky_ad.data(), sky_ad.size() * sizeof(double));
+  std::memcpy(hp + align_up(sky_ad.size() * sizeof(double)), ndev.data(), ndev.size() * sizeof(NodeDev));
+  HIP_TRY(hipMemcpyAsync(p->ws, hp, desc_bytes, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipEventRecord(p->staged, st));
+  p->staged_pending = true;
+
+  GridOut go{};
+  go.mode = out->mode;
+  go.k_lo = out->k_lo;
+  go.k_hi = out->k_hi;
+  go.threshold = out->threshold;
+  go.F = out->F;
+  go.Fmax = out->Fmax;
+  go.kmax = out->kmax;
+  go.xing = out->crossings;
+  go.n_xing = out->n_crossings;
+  go.max_xing = out->max_crossings;
+  if (out->mode == 2) HIP_TRY(fsk::zero_u64(out->n_crossings, st));
+
+  const double er = (double)elem_real(prec);
+  for (const auto& b : batches) {
+    const SegPlan& sp = p->segs[b.seg];
+    const SegDev& d = sp.dev;
+    const int nblk = fsk::sky_prep_blocks(d);
+    const int64_t qstride = (int64_t)d.R * d.Ceff;
+    const double rec_bytes = 4.0 * er * (double)qstride;  // one sky record
+    HIP_TRY(timed(p, FSTAT_K_OTHER, 0.0, st, [&] { return fsk::sky_setup(d_ad + 2 * b.sky0, b.nsky, d, d_sky, st); }));
+    HIP_TRY(timed(p, FSTAT_K_SKY, rec_bytes * b.nsky, st, [&] {
+      return fsk::sky_prep(prec, d, d_sky, b.nsky, d_quads, qstride, d_abc, nblk, st);
+    }));
+    HIP_TRY(timed(p, FSTAT_K_OTHER, 0.0, st, [&] { return fsk::sky_finalize(d, d_abc, nblk, b.nsky, d_coef, st); }));
+    for (int n0 = 0; n0 < b.nnode; n0 += node_cap) {
+      const int nn = std::min(node_cap, b.nnode - n0);
+      const NodeDev* dn = d_nodes + b.node0 + n0;
+      const double spill = 4.0 * er * (double)d.nfft * nn;
+      const double outb = out->mode == 0 ? er * (double)(out->k_hi - out->k_lo) * nn : 0.0;
+      HIP_TRY(timed(p, FSTAT_K_PASS1, spill + rec_bytes * nn / std::max(1, b.nnode / b.nsky), st, [&] {
+        return fsk::grid_pass1(prec, d.C, d, d_quads, qstride, d_sky, dn, nn, sp.twC, sp.twlo, sp.twhi, d_spill, st);
+      }));
+      HIP_TRY(timed(p, FSTAT_K_PASS2, spill + outb, st, [&] {
+        return fsk::grid_pass2(prec, d.R, sp.B2, d, d_spill, dn, nn, d_coef, sp.twR, go, d_part, st);
+      }));
+      if (out->mode == 1)
+        HIP_TRY(timed(p, FSTAT_K_OTHER, 0.0, st,
+                      [&] { return fsk::max_finalize(d_part, d.C / sp.B2, dn, nn, prec, go, st); }));
+    }
+  }
+  return FSTAT_OK;
+}
+
+fstat_status fstat_profile(fstat_plan_t p, int32_t enable) {
+  if (!p) return FSTAT_EINVAL;
+  DeviceGuard guard(p->device);
+  if (!guard.ok) return FSTAT_EDEVICE;
+  HIP_TRY(hipDeviceSynchronize());
+  for (auto& pr : p->prof.pending) p->prof.pool.push_back(pr);
+  p->prof.pending.clear();
+  for (auto& k : p->prof.kinds) k = ProfKind{};
+  p->prof.on = enable != 0;
+  return FSTAT_OK;
+}
+
+fstat_status fstat_profile_read(fstat_plan_t p, int32_t kind, int64_t* launches, double* ms, double* bytes) {
+  if (!p || kind < 0 || kind >= 4) return FSTAT_EINVAL;
+  DeviceGuard guard(p->device);
+  if (!guard.ok) return FSTAT_EDEVICE;
+  HIP_TRY(hipDeviceSynchronize());
+  for (auto& pr : p->prof.pending) {
+    float t = 0.f;
+    HIP_TRY(hipEventElapsedTime(&t, pr.a, pr.b));
+    ProfKind& k = p->prof.kinds[pr.kind];
+    k.launches += 1;
+    k.ms += t;
+    k.bytes += pr.bytes;
+    p->prof.pool.push_back(pr);
+  }
+  p->prof.pending.clear();
+  const ProfKind& k = p->prof.kinds[kind];
+  if (launches) *launches = k.launches;
+  if (ms) *ms = k.ms;
+  if (bytes) *bytes = k.bytes;
+  return FSTAT_OK;
+}
+
+fstat_status fstat_eval(fstat_plan_t p, const double* params, const int32_t* seg, int64_t n, double* F,
+                        double* state, void* hip_stream) {
+  if (!p || !params || n <= 0 || !F) return FSTAT_EINVAL;
+  if (n > (int64_t)INT32_MAX) return FSTAT_EUNSUPPORTED;
+  DeviceGuard guard(p->device);
+  if (!guard.ok) return FSTAT_EDEVICE;
+  return from_hip(fsk::grad_forward(p->d_segs, (int)p->segs.size(), seg, params, n, F, state, (hipStream_t)hip_stream));
+}
+
+fstat_status fstat_adjoint(fstat_plan_t p, const double* params, const int32_t* seg, int64_t n, const double* state,
+                           const double* gF, double* dparams, void* hip_stream) {
+  if (!p || !params || n <= 0 || !state || !dparams) return FSTAT_EINVAL;
+  if (n > (int64_t)INT32_MAX) return FSTAT_EUNSUPPORTED;
+  DeviceGuard guard(p->device);
+  if (!guard.ok) return FSTAT_EDEVICE;
+  return from_hip(fsk::grad_adjoint(p->d_segs, (int)p->segs.size(), seg, params, n, state, gF, dparams, (hipStream_t)hip_stream));
+}
+
+fstat_status fstat_grad(fstat_plan_t p, const double* params, const int32_t* seg, int64_t n, double* F, double* dF,
+                        void* hip_stream) {
+  if (!p || !params || n <= 0 || !F) return FSTAT_EINVAL;
+  if (n > (int64_t)INT32_MAX) return FSTAT_EUNSUPPORTED;
+  DeviceGuard guard(p->device);
+  if (!guard.ok) return FSTAT_EDEVICE;
+  hipStream_t st = (hipStream_t)hip_stream;
+  if (!dF) return from_hip(fsk::grad_forward(p->d_segs, (int)p->segs.size(), seg, params, n, F, nullptr, st));
+  fstat_status rc = ensure_ws(p, align_up((size_t)n * FSTATE * sizeof(double)));
+  if (rc != FSTAT_OK) return rc;
+  double* state = (double*)p->ws;
+  HIP_TRY(fsk::grad_forward(p->d_segs, (int)p->segs.size(), seg, params, n, F, state, st));
+  return from_hip(fsk::grad_adjoint(p->d_segs, (int)p->segs.size(), seg, params, n, state, nullptr, dF, st));
+}
+
+fstat_status fstat_demod_series(fstat_plan_t p, const fstat_node* node, double* out, void* hip_stream) {
+  if (!p || !node || !out) return FSTAT_EINVAL;
+  if (node->seg < 0 || node->seg >= (int32_t)p->segs.size()) return FSTAT_EINVAL;
+  DeviceGuard guard(p->device);
+  if (!guard.ok) return FSTAT_EDEVICE;
+  hipStream_t st = (hipStream_t)hip_stream;
+  const SegDev& d = p->segs[node->seg].dev;
+  const int nblk = fsk::sky_prep_blocks(d);
+  const size_t qbytes = (size_t)d.R * d.Ceff * 4 * elem_real(p->prec);
+  const size_t need = 256 + align_up(qbytes) + align_up((size_t)nblk * 3 * sizeof(double)) + align_up(sizeof(SkyConst)) +
+                      align_up(sizeof(SkyCoef)) + 1024;
+  fstat_status rc = ensure_ws(p, need);
+  if (rc != FSTAT_OK) return rc;
+  rc = ensure_pinned(p, 256);
+  if (rc != FSTAT_OK) return rc;
+  Carve cv{(char*)p->ws};
+  double* d_ad = cv.take<double>(2);
+  void* d_quads = cv.take<char>(qbytes);
+  double* d_abc = cv.take<double>((size_t)nblk * 3);
+  SkyConst* d_sky = cv.take<SkyConst>(1);
+  double* hp = (double*)p->pinned;
+  hp[0] = node->alpha;
+  hp[1] = node->delta;
+  HIP_TRY(hipMemcpyAsync(d_ad, hp, 2 * sizeof(double), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipEventRecord(p->staged, st));
+  p->staged_pending = true;
+  const int64_t qstride = (int64_t)d.R * d.Ceff;
+  HIP_TRY(fsk::sky_setup(d_ad, 1, d, d_sky, st));
+  HIP_TRY(fsk::sky_prep(p->prec, d, d_sky, 1, d_quads, qstride, d_abc, nblk, st));
+  return from_hip(fsk::demod_series(p->prec, d, d_sky, d_quads, qstride, node->fdot, out, st));
+}
+
+}  // extern "C"

@@ -1,0 +1,287 @@
+// F at continuous parameters and its adjoint (candidate refinement off the
+// grid, after the coarse search of Sec. VI C), all FP64.
+//
+// Forward, per candidate (f, fdot, alpha, delta), over the barycentric grid
+// t_b_j = t_b0 + j dt (the method of Sec. VI A with the FFT kernel replaced by
+// e^{-2 pi i f j dt}):
+//   S_a = sum_j w_a,j e_j,  w_a,j = x(t_j) a(t_j),  e_j = e^{-2 pi i cyc_j},
+//   cyc_j = f_ref dphi_m(t_j) + fdot (t_j^2/2 + phi_m(t_j) t_j) + f j dt,
+// (dphi_m = phi_m - phi_m(0); the constant f_ref phi_m(0) is a common phase),
+// likewise S_b, and A, B, C over the detector samples; F as in fstat_grid.
+//
+// Adjoint: with F = num / D, num = B|S_a|^2 + A|S_b|^2 - 2C Re(S_a S_b*),
+// D = sigma^2 (AB - C^2), a change dS_a moves F by Re(conj(g_a) dS_a) with
+// g_a = 2 (B S_a - C S_b)/D (and g_b = 2 (A S_b - C S_a)/D).  Per sample,
+//   dF/dtheta += dw_a Re(E_a) + 2 pi w_a dcyc Im(E_a) + (same for b),
+//   E_a = conj(g_a) e_j,
+// plus F_A dA/dtheta + F_B dB/dtheta + F_C dC/dtheta from the detector-grid
+// sums.  The sample-level derivatives go through t_j by implicit
+// differentiation of t_j + phi_m(t_j) = t_b0(alpha, delta) + j dt:
+//   dt_j/dtheta = (dt_b0/dtheta - dphi_m/dtheta(t_j)) / (1 + phi_m'(t_j)).
+// The forward state (S_a, S_b, A, B, C) is kept; the resampled series is
+// recomputed, never stored.
+#include "demod.h"
+#include "internal.h"
+
+namespace {
+
+constexpr int GB = 256;
+constexpr double TWO_PI = 6.283185307179586476925286766559;
+
+__device__ __forceinline__ double wsum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  return v;
+}
+
+// fixed-order block sum of NV values; results valid in thread 0
+template <int NV>
+__device__ __forceinline__ void block_sums(double (&v)[NV], double* sh) {
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) v[i] = wsum(v[i]);
+  if ((tid & 63) == 0)
+#pragma unroll
+    for (int i = 0; i < NV; ++i) sh[(tid >> 6) * NV + i] = v[i];
+  __syncthreads();
+  if (tid == 0) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      double s = 0.0;
+      for (int w = 0; w < GB / 64; ++w) s += sh[w * NV + i];
+      v[i] = s;
+    }
+  }
+}
+
+// interpolated x and dx/du at fractional sample position u
+__device__ __forceinline__ void interp_d(const SegDev& sg, double u, double& xr, double& dxdu) {
+  xr = 0.0;
+  dxdu = 0.0;
+  const int64_t n = sg.n;
+  if (!(u >= -SPAN_EPS && u <= (double)(n - 1) + SPAN_EPS)) return;
+  u = fmin(fmax(u, 0.0), (double)(n - 1));
+  if (sg.interp == 0) {
+    xr = sg.x[(int64_t)floor(u + 0.5)];
+    return;
+  }
+  const double v = 2.0 * u;
+  int64_t i = (int64_t)floor(v);
+  if (i > 2 * n - 2) i = 2 * n - 2;
+  const double s = v - (double)i;
+  const double y0 = sg.y[i], y1 = sg.y[i + 1];
+  if (sg.interp == 1) {
+    xr = (1.0 - s) * y0 + s * y1;
+    dxdu = 2.0 * (y1 - y0);
+  } else {
+    const double m0 = sg.M[i], m1 = sg.M[i + 1], r = 1.0 - s;
+    xr = r * y0 + s * y1 + ((r * r * r - r) * m0 + (s * s * s - s) * m1) / 6.0;
+    dxdu = 2.0 * (y1 - y0 + ((1.0 - 3.0 * r * r) * m0 + (3.0 * s * s - 1.0) * m1) / 6.0);
+  }
+}
+
+struct Cand {
+  double f, fdot, alpha, delta;
+};
+
+__device__ __forceinline__ void setup_sky(const SegDev& sg, const Cand& c, SkyConst& k) {
+  sky_const(c.alpha, c.delta, sg.geo, k);
+  k.tb0 = roemer(k, ephem(sg.geo, 0.0));
+}
+
+__global__ void __launch_bounds__(GB)
+k_eval(const SegDev* __restrict__ segs, int nseg, const int32_t* __restrict__ segi,
+       const double* __restrict__ params, double* __restrict__ Fout, double* __restrict__ state) {
+  __shared__ double sh[(GB / 64) * 7];
+  const int64_t ci = blockIdx.x;
+  const int si = segi ? segi[ci] : 0;
+  if (si < 0 || si >= nseg) {  // invalid segment index: NaN result, nothing read
+    if (threadIdx.x == 0) Fout[ci + threadIdx.x] = __builtin_nan("");
+    return;
+  }
+  const SegDev sg = segs[si];
+  const Cand c{params[4 * ci], params[4 * ci + 1], params[4 * ci + 2], params[4 * ci + 3]};
+  SkyConst k;
+  setup_sky(sg, c, k);
+  double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+  for (int64_t j = threadIdx.x; j < sg.n; j += GB) {
+    EphemD e;
+    double dpm;
+    const double t = ssb_to_detector(sg.geo, k, (double)j * sg.dt, e, dpm);
+    const double pm = k.tb0 + dpm;
+    double xr, dxdu;
+    interp_d(sg, t / sg.dt, xr, dxdu);
+    double a, b;
+    amp_ab(k, hour_angle(k, e.cth, e.sth), a, b);
+    double cyc = sg.f_ref * dpm + c.fdot * (0.5 * t * t + pm * t) + c.f * ((double)j * sg.dt);
+    cyc -= rint(cyc);
+    double s, co;
+    sincospi(2.0 * cyc, &s, &co);
+    acc[0] += xr * a * co;
+    acc[1] -= xr * a * s;
+    acc[2] += xr * b * co;
+    acc[3] -= xr * b * s;
+    // detector-grid sums
+    const Ephem ed = ephem(sg.geo, (double)j * sg.dt);
+    double ad, bd;
+    amp_ab(k, hour_angle(k, ed), ad, bd);
+    const double m = sg.mask ? (sg.mask[j] ? 1.0 : 0.0) : 1.0;
+    acc[4] += m * ad * ad;
+    acc[5] += m * bd * bd;
+    acc[6] += m * ad * bd;
+  }
+  block_sums<7>(acc, sh);
+  if (threadIdx.x == 0) {
+    const double Sar = acc[0], Sai = acc[1], Sbr = acc[2], Sbi = acc[3];
+    const double A = acc[4], B = acc[5], C = acc[6];
+    const double num = B * (Sar * Sar + Sai * Sai) + A * (Sbr * Sbr + Sbi * Sbi) - 2.0 * C * (Sar * Sbr + Sai * Sbi);
+    Fout[ci + threadIdx.x] = num / (sg.sigma2 * (A * B - C * C));
+    if (state) {
+      double* st = state + FSTATE * ci + threadIdx.x;
+      st[0] = Sar;
+      st[1] = Sai;
+      st[2] = Sbr;
+      st[3] = Sbi;
+      st[4] = A;
+      st[5] = B;
+      st[6] = C;
+      st[7] = 0.0;
+    }
+  }
+}
+
+struct Partials {  // phi_m partials w.r.t. alpha, delta, and time derivative
+  double al, de, T;
+};
+__device__ __forceinline__ Partials roemer_partials(const SegDev& sg, const SkyConst& k, const Ephem& e) {
+  const SegGeo& g = sg.geo;
+  const double wo = TWO_PI * g.orb_rate_c, wr = TWO_PI * g.sid_rate_c;
+  Partials p;
+  p.al = k.nx_a * (e.xes + e.xe) + k.nye_a * e.yes + k.ny_a * e.ye + k.nz_a * e.ze;
+  p.de = k.nx_d * (e.xes + e.xe) + k.nye_d * e.yes + k.ny_d * e.ye + k.nz_d * e.ze;
+  const double dxes = -g.orb_r * wo * e.sor, dyes = g.orb_r * wo * e.cor;
+  const double dxe = -g.site_rc * wr * e.sth, dye = g.site_rc * wr * e.cth;
+  p.T = k.nx * (dxes + dxe) + k.nye * dyes + k.ny * dye;
+  return p;
+}
+
+struct AbPartials {
+  double a, b, ax, bx, ad, bd;  // values, d/dx (x = alpha - sidereal angle), d/ddelta
+};
+__device__ __forceinline__ AbPartials ab_partials(const SkyConst& k, const HourAngle& h) {
+  AbPartials r;
+  amp_ab(k, h, r.a, r.b);
+  r.ax = -2.0 * k.a2c * h.s2 + 2.0 * k.a2s * h.c2 - k.a1c * h.s1 + k.a1s * h.c1;
+  r.bx = -2.0 * k.b2c * h.s2 + 2.0 * k.b2s * h.c2 - k.b1c * h.s1 + k.b1s * h.c1;
+  r.ad = k.da2c * h.c2 + k.da2s * h.s2 + k.da1c * h.c1 + k.da1s * h.s1 + k.da0;
+  r.bd = k.db2c * h.c2 + k.db2s * h.s2 + k.db1c * h.c1 + k.db1s * h.s1;
+  return r;
+}
+
+__global__ void __launch_bounds__(GB)
+k_adjoint(const SegDev* __restrict__ segs, int nseg, const int32_t* __restrict__ segi,
+          const double* __restrict__ params, const double* __restrict__ state, const double* __restrict__ gF,
+          double* __restrict__ dp) {
+  __shared__ double sh[(GB / 64) * 4];
+  const int64_t ci = blockIdx.x;
+  const int si = segi ? segi[ci] : 0;
+  if (si < 0 || si >= nseg) {
+    if (threadIdx.x < 4) dp[4 * ci + threadIdx.x] = __builtin_nan("");
+    return;
+  }
+  const SegDev sg = segs[si];
+  const Cand c{params[4 * ci], params[4 * ci + 1], params[4 * ci + 2], params[4 * ci + 3]};
+  SkyConst k;
+  setup_sky(sg, c, k);
+  const double* st = state + FSTATE * ci;
+  const double Sar = st[0], Sai = st[1], Sbr = st[2], Sbi = st[3], A = st[4], B = st[5], C = st[6];
+  const double s2 = sg.sigma2;
+  const double D = s2 * (A * B - C * C);
+  const double Sa2 = Sar * Sar + Sai * Sai, Sb2 = Sbr * Sbr + Sbi * Sbi, Rab = Sar * Sbr + Sai * Sbi;
+  const double num = B * Sa2 + A * Sb2 - 2.0 * C * Rab;
+  // adjoint weights of S_a, S_b and partials of F w.r.t. A, B, C
+  const double gar = 2.0 * (B * Sar - C * Sbr) / D, gai = 2.0 * (B * Sai - C * Sbi) / D;
+  const double gbr = 2.0 * (A * Sbr - C * Sar) / D, gbi = 2.0 * (A * Sbi - C * Sai) / D;
+  const double FA = Sb2 / D - num * s2 * B / (D * D);
+  const double FB = Sa2 / D - num * s2 * A / (D * D);
+  const double FC = -2.0 * Rab / D + num * s2 * 2.0 * C / (D * D);
+  const double wr = TWO_PI * sg.geo.sid_rate_c;
+  const Partials p0 = roemer_partials(sg, k, ephem(sg.geo, 0.0));  // d t_b0 / d(alpha, delta)
+
+  double acc[4] = {0, 0, 0, 0};
+  for (int64_t j = threadIdx.x; j < sg.n; j += GB) {
+    const double jdt = (double)j * sg.dt;
+    EphemD ed;
+    double dpm;
+    const double t = ssb_to_detector(sg.geo, k, jdt, ed, dpm);
+    const double pm = k.tb0 + dpm;
+    const Ephem e = ephem(sg.geo, t);  // absolute positions for the partials
+    double xr, dxdu;
+    interp_d(sg, t / sg.dt, xr, dxdu);
+    const AbPartials ab = ab_partials(k, hour_angle(k, ed.cth, ed.sth));
+    const Partials pp = roemer_partials(sg, k, e);
+    double cyc = sg.f_ref * dpm + c.fdot * (0.5 * t * t + pm * t) + c.f * jdt;
+    cyc -= rint(cyc);
+    double s, co;
+    sincospi(2.0 * cyc, &s, &co);
+    // E = conj(g) e, e = (co, -s)
+    const double Ear = gar * co - gai * s, Eai = -gar * s - gai * co;
+    const double Ebr = gbr * co - gbi * s, Ebi = -gbr * s - gbi * co;
+    const double wa = xr * ab.a, wb = xr * ab.b;
+    // f and fdot: phase only
+    acc[0] += TWO_PI * jdt * (wa * Eai + wb * Ebi);
+    const double Q = 0.5 * t * t + pm * t;
+    acc[1] += TWO_PI * Q * (wa * Eai + wb * Ebi);
+    // alpha, delta
+    const double den = 1.0 + pp.T;
+#pragma unroll
+    for (int th = 0; th < 2; ++th) {
+      const double dtb0 = th == 0 ? p0.al : p0.de;
+      const double dpmx = th == 0 ? pp.al : pp.de;
+      const double dtj = (dtb0 - dpmx) / den;
+      const double dxr = dxdu * dtj / sg.dt;
+      const double dx = (th == 0 ? 1.0 : 0.0) - wr * dtj;
+      const double da = ab.ax * dx + (th == 1 ? ab.ad : 0.0);
+      const double db = ab.bx * dx + (th == 1 ? ab.bd : 0.0);
+      const double dpm = dpmx + pp.T * dtj;
+      const double dcyc = sg.f_ref * dpm + c.fdot * (t * dtj + dpm * t + pm * dtj);
+      const double dwa = dxr * ab.a + xr * da, dwb = dxr * ab.b + xr * db;
+      acc[2 + th] += dwa * Ear + TWO_PI * wa * dcyc * Eai + dwb * Ebr + TWO_PI * wb * dcyc * Ebi;
+    }
+    // A, B, C on the detector samples
+    const AbPartials g = ab_partials(k, hour_angle(k, ephem(sg.geo, jdt)));
+    const double m = sg.mask ? (sg.mask[j] ? 1.0 : 0.0) : 1.0;
+    acc[2] += m * (FA * 2.0 * g.a * g.ax + FB * 2.0 * g.b * g.bx + FC * (g.ax * g.b + g.a * g.bx));
+    acc[3] += m * (FA * 2.0 * g.a * g.ad + FB * 2.0 * g.b * g.bd + FC * (g.ad * g.b + g.a * g.bd));
+  }
+  block_sums<4>(acc, sh);
+  if (threadIdx.x == 0) {
+    const double w = gF ? gF[ci] : 1.0;
+    double* o = dp + 4 * ci + threadIdx.x;
+    o[0] = w * acc[0];
+    o[1] = w * acc[1];
+    o[2] = w * acc[2];
+    o[3] = w * acc[3];
+  }
+}
+
+}  // namespace
+
+namespace fsk {
+
+hipError_t grad_forward(const SegDev* d_segs, int nseg, const int32_t* d_seg, const double* d_params, int64_t n,
+                        double* d_F, double* d_state, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_eval, dim3((unsigned)n), dim3(GB), 0, st, d_segs, nseg, d_seg, d_params, d_F, d_state);
+  return hipGetLastError();
+}
+
+hipError_t grad_adjoint(const SegDev* d_segs, int nseg, const int32_t* d_seg, const double* d_params, int64_t n,
+                        const double* d_state, const double* d_gF, double* d_dp, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_adjoint, dim3((unsigned)n), dim3(GB), 0, st, d_segs, nseg, d_seg, d_params, d_state, d_gF,
+                     d_dp);
+  return hipGetLastError();
+}
+
+}  // namespace fsk

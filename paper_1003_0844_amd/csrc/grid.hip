@@ -1,0 +1,259 @@
+// The per-node hot path: demodulation fused into the first FFT pass, the
+// second pass fused with the F combination (Sec. VI A-B, Eqs. ia, DFT, OS).
+//
+// nfft = R * C.  Sample j = r + R c (r < R, c < C), bin k = C k1 + k2
+// (k1 < R, k2 < C):
+//   X[C k1 + k2] = sum_r e^{-2 pi i r k1/R} [ e^{-2 pi i r k2/nfft}
+//                                             sum_c x[r + R c] e^{-2 pi i c k2/C} ]
+// Pass 1 (one workgroup per column r of one node): build x_j for the a- and
+//   b-weighted series on the fly from the sky record and the node's spindown,
+//   length-C FFT in LDS, inter-pass twiddle, store Z[r][k2] (a and b
+//   interleaved, 16 B per element in FP32).
+// Pass 2 (one workgroup per block of B2 adjacent k2 of one node): length-R FFT
+//   of each column, keep the bins k < nfft/2 (k1 < R/2), combine
+//   F = (B|S_a|^2 + A|S_b|^2 - 2C Re(S_a S_b*)) / (sigma^2 (AB - C^2)) and write
+//   the map row, the per-node maximum or the threshold crossings.
+// The inter-pass spill Z is the only HBM round trip of a node:
+// 2 x 8 B x nfft written and read in FP32.
+#include "demod.h"
+#include "fft_block.h"
+#include "internal.h"
+
+namespace {
+
+template <typename T>
+constexpr int cfg_B2(int R) {
+  return sizeof(T) == 4 ? (4096 / R < 64 ? 4096 / R : 64) : (2048 / R < 32 ? 2048 / R : 32);
+}
+constexpr int cfg_block(int nb) { return nb < 64 ? 64 : (nb > 256 ? 256 : nb); }
+
+// Map the hardware workgroup id so that consecutive logical column blocks run
+// on the same XCD (the dispatcher deals workgroups round-robin over 8 XCDs):
+// adjacent blocks then share L2 lines of the output rows.
+__device__ __forceinline__ int xcd_local(int bid, int nblk) {
+  if (nblk % 8 != 0) return bid;
+  return (bid % 8) * (nblk / 8) + bid / 8;
+}
+
+template <typename T, int C>
+__global__ void __launch_bounds__(cfg_block(C / 16))
+k_pass1(SegDev sg, const Quad<T>* __restrict__ quads, int64_t qstride, const SkyConst* __restrict__ skies,
+        const NodeDev* __restrict__ nodes, const cpx<T>* __restrict__ twC, const cpx<T>* __restrict__ twlo,
+        const cpx<T>* __restrict__ twhi, Pair<T>* __restrict__ spill) {
+  constexpr int BLOCK = cfg_block(C / 16);
+  __shared__ Pair<T> lds[lds_slots(C, 1)];
+  const int r = blockIdx.x;
+  const int nd = blockIdx.y;
+  const NodeDev node = nodes[nd];
+  const Quad<T>* __restrict__ col = quads + (int64_t)node.sky * qstride + (int64_t)r * sg.Ceff;
+  const double tb0 = skies[node.sky].tb0;
+  const double fdot = node.fdot;
+  const int ceff = sg.Ceff;
+  const int R = sg.R;
+  const double dt = sg.dt;
+  auto load = [&](int c, int) -> Pair<T> {
+    if (c < ceff) return demod_elem<T>(col[c], tb0, (int64_t)r + (int64_t)R * c, dt, fdot);
+    return Pair<T>{{(T)0, (T)0}, {(T)0, (T)0}};
+  };
+  Pair<T>* __restrict__ dst = spill + (int64_t)nd * sg.nfft + (int64_t)r * C;
+  // inter-pass twiddle e^{-2 pi i r k2/nfft} for the outputs k2 = i + q STR of a
+  // butterfly: (table value at r i) x (table value at r STR)^q
+  auto store = [&](int i, int, auto& v, auto str) {
+    constexpr int RS = std::extent<std::remove_reference_t<decltype(v)>>::value;
+    constexpr int STR = decltype(str)::value;
+    const int m0 = r * i, ms = r * STR;  // both < nfft, exact
+    const cpx<T> base = cmul(twhi[m0 >> 12], twlo[m0 & 4095]);
+    const cpx<T> step = cmul(twhi[ms >> 12], twlo[ms & 4095]);
+    cpx<T> pw[RS];
+    powers<RS>(step, pw);
+#pragma unroll
+    for (int q = 0; q < RS; ++q) dst[i + q * STR] = twmul(v[q], cmul(base, pw[q]));
+  };
+  block_fft<Pair<T>, C, 1, BLOCK, -1>(lds, twC, load, store);
+}
+
+template <typename T, int R, int MODE>
+__global__ void __launch_bounds__(cfg_block(cfg_B2<T>(R) * R / 16))
+k_pass2(SegDev sg, const Pair<T>* __restrict__ spill, const NodeDev* __restrict__ nodes,
+        const SkyCoef* __restrict__ coef, const cpx<T>* __restrict__ twR, GridOut out,
+        MaxPartial* __restrict__ part) {
+  constexpr int B2 = cfg_B2<T>(R);
+  constexpr int BLOCK = cfg_block(B2 * R / 16);
+  __shared__ Pair<T> lds[lds_slots(R, B2)];
+  const int nd = blockIdx.y;
+  const int cb = xcd_local(blockIdx.x, gridDim.x);
+  const NodeDev node = nodes[nd];
+  const int C = sg.C;
+  const Pair<T>* __restrict__ src = spill + (int64_t)nd * sg.nfft + (int64_t)cb * B2;
+  auto load = [&](int r, int col) -> Pair<T> { return src[(int64_t)r * C + col]; };
+  const SkyCoef cf = coef[node.sky];
+  const T cB = (T)cf.cB, cA = (T)cf.cA, cC = (T)cf.cC;
+  const int64_t klo = out.k_lo, khi = out.k_hi;
+  double best = -1.0;
+  int64_t bestk = INT64_MAX;
+  auto store1 = [&](int k1, int col, const Pair<T>& v) {
+    if (k1 >= R / 2) return;
+    const int64_t k = (int64_t)C * k1 + (int64_t)cb * B2 + col;
+    if (k < klo || k >= khi) return;
+    // explicit fused operations: every output mode rounds identically
+    const T pa = fma(v.a.x, v.a.x, v.a.y * v.a.y);
+    const T pb = fma(v.b.x, v.b.x, v.b.y * v.b.y);
+    const T re = fma(v.a.x, v.b.x, v.a.y * v.b.y);
+    const T F = fma(cB, pa, fma(cA, pb, -(cC * re)));
+    if constexpr (MODE == 0) {
+      ((T*)out.F)[(int64_t)node.row * (khi - klo) + (k - klo)] = F;
+    } else if constexpr (MODE == 1) {
+      const double f = (double)F;
+      if (f > best || (f == best && k < bestk)) {
+        best = f;
+        bestk = k;
+      }
+    } else {
+      if ((double)F > out.threshold) {
+        const unsigned long long i = atomicAdd(out.n_xing, 1ull);
+        if ((int64_t)i < out.max_xing) ((Crossing*)out.xing)[i] = Crossing{node.row, k, (double)F};
+      }
+    }
+  };
+  auto store = [&](int i, int col, auto& v, auto str) {
+    constexpr int RS = std::extent<std::remove_reference_t<decltype(v)>>::value;
+    constexpr int STR = decltype(str)::value;
+#pragma unroll
+    for (int q = 0; q < RS; ++q) store1(i + q * STR, col, v[q]);
+  };
+  block_fft<Pair<T>, R, B2, BLOCK, -1>(lds, twR, load, store);
+  if constexpr (MODE == 1) {
+    // block arg-max, ties to the lowest bin
+    __shared__ double sf[BLOCK / 64];
+    __shared__ int64_t sk[BLOCK / 64];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const double f2 = __shfl_down(best, o, 64);
+      const int64_t k2 = __shfl_down(bestk, o, 64);
+      if (f2 > best || (f2 == best && k2 < bestk)) {
+        best = f2;
+        bestk = k2;
+      }
+    }
+    if ((threadIdx.x & 63) == 0) {
+      sf[threadIdx.x >> 6] = best;
+      sk[threadIdx.x >> 6] = bestk;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      for (int w = 1; w < BLOCK / 64; ++w)
+        if (sf[w] > best || (sf[w] == best && sk[w] < bestk)) {
+          best = sf[w];
+          bestk = sk[w];
+        }
+      part[(int64_t)nd * gridDim.x + cb] = MaxPartial{best, bestk};
+    }
+  }
+}
+
+template <typename T>
+__global__ void k_max_finalize(const MaxPartial* __restrict__ part, int nparts, const NodeDev* __restrict__ nodes,
+                               int nnodes, T* __restrict__ Fmax, int64_t* __restrict__ kmax) {
+  const int nd = blockIdx.x * blockDim.x + threadIdx.x;
+  if (nd >= nnodes) return;
+  double best = -1.0;
+  int64_t bk = INT64_MAX;
+  for (int i = 0; i < nparts; ++i) {
+    const MaxPartial p = part[(int64_t)nd * nparts + i];
+    if (p.F > best || (p.F == best && p.k < bk)) {
+      best = p.F;
+      bk = p.k;
+    }
+  }
+  Fmax[nodes[nd].row] = (T)best;
+  kmax[nodes[nd].row] = bk;
+}
+
+__global__ void k_zero_u64(unsigned long long* p) {
+  if (threadIdx.x == 0) p[threadIdx.x] = 0ull;
+}
+
+template <typename T>
+hipError_t launch_pass1(int C, const SegDev& seg, const void* quads, int64_t qstride, const SkyConst* sky,
+                        const NodeDev* nodes, int nnodes, const void* twC, const void* twlo, const void* twhi,
+                        void* spill, hipStream_t st) {
+  dim3 grid(seg.R, nnodes);
+#define P1(CC)                                                                                              \
+  case CC:                                                                                                  \
+    hipLaunchKernelGGL((k_pass1<T, CC>), grid, dim3(cfg_block(CC / 16)), 0, st, seg, (const Quad<T>*)quads, \
+                       qstride, sky, nodes, (const cpx<T>*)twC, (const cpx<T>*)twlo, (const cpx<T>*)twhi,   \
+                       (Pair<T>*)spill);                                                                    \
+    break;
+  switch (C) {
+    P1(64) P1(128) P1(256) P1(512) P1(1024) P1(2048) P1(4096)
+    default: return hipErrorInvalidValue;
+  }
+#undef P1
+  return hipGetLastError();
+}
+
+template <typename T, int MODE>
+hipError_t launch_pass2_mode(int R, const SegDev& seg, const void* spill, const NodeDev* nodes, int nnodes,
+                             const SkyCoef* coef, const void* twR, const GridOut& out, MaxPartial* part,
+                             hipStream_t st) {
+#define P2(RR)                                                                                      \
+  case RR: {                                                                                        \
+    constexpr int B2 = cfg_B2<T>(RR);                                                               \
+    dim3 grid(seg.C / B2, nnodes);                                                                  \
+    hipLaunchKernelGGL((k_pass2<T, RR, MODE>), grid, dim3(cfg_block(B2 * RR / 16)), 0, st, seg,     \
+                       (const Pair<T>*)spill, nodes, coef, (const cpx<T>*)twR, out, part);          \
+  } break;
+  switch (R) {
+    P2(16) P2(32) P2(64) P2(128) P2(256) P2(512) P2(1024)
+    default: return hipErrorInvalidValue;
+  }
+#undef P2
+  return hipGetLastError();
+}
+
+}  // namespace
+
+namespace fsk {
+
+int pass2_b2(int prec, int R) { return prec == 0 ? cfg_B2<float>(R) : cfg_B2<double>(R); }
+
+hipError_t grid_pass1(int prec, int C, const SegDev& seg, const void* quads, int64_t qstride, const SkyConst* sky,
+                      const NodeDev* nodes, int nnodes, const void* twC, const void* twlo, const void* twhi,
+                      void* spill, hipStream_t st) {
+  if (nnodes <= 0) return hipSuccess;
+  if (prec == 0) return launch_pass1<float>(C, seg, quads, qstride, sky, nodes, nnodes, twC, twlo, twhi, spill, st);
+  return launch_pass1<double>(C, seg, quads, qstride, sky, nodes, nnodes, twC, twlo, twhi, spill, st);
+}
+
+hipError_t grid_pass2(int prec, int R, int, const SegDev& seg, const void* spill, const NodeDev* nodes, int nnodes,
+                      const SkyCoef* coef, const void* twR, const GridOut& out, MaxPartial* part, hipStream_t st) {
+  if (nnodes <= 0) return hipSuccess;
+  if (prec == 0) {
+    if (out.mode == 0) return launch_pass2_mode<float, 0>(R, seg, spill, nodes, nnodes, coef, twR, out, part, st);
+    if (out.mode == 1) return launch_pass2_mode<float, 1>(R, seg, spill, nodes, nnodes, coef, twR, out, part, st);
+    return launch_pass2_mode<float, 2>(R, seg, spill, nodes, nnodes, coef, twR, out, part, st);
+  }
+  if (out.mode == 0) return launch_pass2_mode<double, 0>(R, seg, spill, nodes, nnodes, coef, twR, out, part, st);
+  if (out.mode == 1) return launch_pass2_mode<double, 1>(R, seg, spill, nodes, nnodes, coef, twR, out, part, st);
+  return launch_pass2_mode<double, 2>(R, seg, spill, nodes, nnodes, coef, twR, out, part, st);
+}
+
+hipError_t max_finalize(const MaxPartial* part, int nparts, const NodeDev* nodes, int nnodes, int prec,
+                        const GridOut& out, hipStream_t st) {
+  if (nnodes <= 0) return hipSuccess;
+  dim3 grid((nnodes + 63) / 64), block(64);
+  if (prec == 0)
+    hipLaunchKernelGGL(k_max_finalize<float>, grid, block, 0, st, part, nparts, nodes, nnodes, (float*)out.Fmax,
+                       out.kmax);
+  else
+    hipLaunchKernelGGL(k_max_finalize<double>, grid, block, 0, st, part, nparts, nodes, nnodes,
+                       (double*)out.Fmax, out.kmax);
+  return hipGetLastError();
+}
+
+hipError_t zero_u64(unsigned long long* p, hipStream_t st) {
+  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, st, p);
+  return hipGetLastError();
+}
+
+}  // namespace fsk

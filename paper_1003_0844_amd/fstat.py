@@ -1,0 +1,357 @@
+"""Python binding of libfstat.so (include/fstat.h): argument marshalling only.
+
+Device memory comes from torch tensors on the plan's GPU and work runs on the
+current torch stream of that device; every arithmetic step of the method runs
+in the HIP kernels of the library.  If the library is missing or cannot be
+loaded, importing this module raises: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfstat.so")
+
+NEAREST, LINEAR_UP2, CUBIC_UP2 = 0, 1, 2
+FP32, FP64 = 0, 1
+OUT_MAP, OUT_MAX, OUT_CROSSINGS = 0, 1, 2
+STATE = 8
+
+OK, EINVAL, ENOTINTDAYS, ENOMEM, EDEVICE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+
+C_LIGHT = 299_792_458.0
+AU = 1.495978707e11
+R_EARTH = 6.378140e6
+SIDEREAL_DAY = 86164.0
+YEAR = 365.256363004 * 86400.0
+
+
+class FStatError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__("%s: %s (%d)" % (what, lib().fstat_strerror(status).decode(), status))
+        self.status = status
+
+
+# --------------------------------------------------------------------------
+# C structures
+# --------------------------------------------------------------------------
+class _Detector(ctypes.Structure):
+    _fields_ = [("lat_rad", ctypes.c_double), ("lon_rad", ctypes.c_double), ("gamma_rad", ctypes.c_double),
+                ("zeta_rad", ctypes.c_double), ("radius_m", ctypes.c_double)]
+
+
+class _Ephemeris(ctypes.Structure):
+    _fields_ = [("obliquity_rad", ctypes.c_double), ("orbit_radius_m", ctypes.c_double),
+                ("orbit_omega", ctypes.c_double), ("orbit_phase0", ctypes.c_double),
+                ("sidereal_day_s", ctypes.c_double), ("gmst0_rad", ctypes.c_double)]
+
+
+class _Segment(ctypes.Structure):
+    _fields_ = [("x", ctypes.POINTER(ctypes.c_double)), ("n", ctypes.c_int64), ("dt", ctypes.c_double),
+                ("n_sidereal_days", ctypes.c_int32), ("t0", ctypes.c_double),
+                ("mask", ctypes.POINTER(ctypes.c_uint8)), ("f_ref_hz", ctypes.c_double),
+                ("sigma2", ctypes.c_double), ("nfft", ctypes.c_int64)]
+
+
+class _Options(ctypes.Structure):
+    _fields_ = [("interp", ctypes.c_int32), ("prec", ctypes.c_int32), ("device", ctypes.c_int32),
+                ("max_batch", ctypes.c_int32)]
+
+
+class _Out(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("pad", ctypes.c_int32), ("k_lo", ctypes.c_int64),
+                ("k_hi", ctypes.c_int64), ("threshold", ctypes.c_double), ("F", ctypes.c_void_p),
+                ("Fmax", ctypes.c_void_p), ("kmax", ctypes.c_void_p), ("crossings", ctypes.c_void_p),
+                ("n_crossings", ctypes.c_void_p), ("max_crossings", ctypes.c_int64)]
+
+
+NODE_DTYPE = np.dtype([("alpha", "<f8"), ("delta", "<f8"), ("fdot", "<f8"), ("seg", "<i4"), ("pad", "<i4")])
+CROSSING_DTYPE = np.dtype([("node", "<i8"), ("k", "<i8"), ("F", "<f8")])
+
+EXPORTS = ("fstat_plan", "fstat_grid", "fstat_eval", "fstat_adjoint", "fstat_grad", "fstat_plan_info",
+           "fstat_demod_series", "fstat_profile", "fstat_profile_read", "fstat_destroy", "fstat_strerror")
+K_SKY, K_PASS1, K_PASS2, K_OTHER = 0, 1, 2, 3
+
+_lib = None
+
+
+def lib():
+    """The loaded library.  Raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libfstat.so is not built (run __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i64, i32, P = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.POINTER
+        L.fstat_plan.argtypes = [P(_Segment), i32, P(_Detector), P(_Ephemeris), P(_Options), P(vp)]
+        L.fstat_grid.argtypes = [vp, vp, i64, P(_Out), vp]
+        L.fstat_eval.argtypes = [vp, vp, vp, i64, vp, vp, vp]
+        L.fstat_adjoint.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp]
+        L.fstat_grad.argtypes = [vp, vp, vp, i64, vp, vp, vp]
+        L.fstat_plan_info.argtypes = [vp, i32, P(i64), P(i64), P(ctypes.c_double), P(i32), P(i32)]
+        L.fstat_demod_series.argtypes = [vp, vp, vp, vp]
+        L.fstat_profile.argtypes = [vp, i32]
+        L.fstat_profile_read.argtypes = [vp, i32, P(i64), P(ctypes.c_double), P(ctypes.c_double)]
+        L.fstat_destroy.argtypes = [vp]
+        L.fstat_strerror.argtypes = [i32]
+        L.fstat_strerror.restype = ctypes.c_char_p
+        L.fstat_destroy.restype = None
+        for name in ("fstat_plan", "fstat_grid", "fstat_eval", "fstat_adjoint", "fstat_grad", "fstat_plan_info",
+                     "fstat_demod_series", "fstat_profile", "fstat_profile_read"):
+            getattr(L, name).restype = i32
+        _lib = L
+    return _lib
+
+
+def _check(status: int, what: str):
+    if status != OK:
+        raise FStatError(status, what)
+
+
+# --------------------------------------------------------------------------
+# Python-side descriptions
+# --------------------------------------------------------------------------
+@dataclass(frozen=True)
+class Detector:
+    lat: float
+    lon: float
+    gamma: float
+    zeta: float = math.pi / 2
+    radius: float = R_EARTH
+
+
+@dataclass(frozen=True)
+class Ephemeris:
+    obliquity: float = math.radians(23.44)
+    orbit_radius: float = AU
+    orbit_omega: float = 2.0 * math.pi / YEAR
+    orbit_phase0: float = 0.0
+    sidereal_day: float = SIDEREAL_DAY
+    gmst0: float = 0.0
+
+
+def default_detector() -> Detector:
+    """Latitude 43.63 deg, longitude 10.5 deg, first arm 19.4 deg east of
+    North with 90-deg arms: bisector 115.6 deg counter-clockwise from East."""
+    return Detector(lat=math.radians(43.63), lon=math.radians(10.5), gamma=math.radians(115.6))
+
+
+def detector_spec(d) -> Detector:
+    """Any object with lat, lon, gamma, zeta, radius attributes."""
+    return Detector(float(d.lat), float(d.lon), float(d.gamma), float(d.zeta), float(d.radius))
+
+
+def ephemeris_spec(e) -> Ephemeris:
+    return Ephemeris(float(e.obliquity), float(e.orbit_radius), float(e.orbit_omega), float(e.orbit_phase0),
+                     float(e.sidereal_day), float(e.gmst0))
+
+
+@dataclass
+class SegmentSpec:
+    x: np.ndarray
+    dt: float
+    n_days: int
+    t0: float = 0.0
+    mask: Optional[np.ndarray] = None
+    f_ref: float = 435.1875
+    sigma2: float = 1.0
+    nfft: int = 0
+
+
+def nodes_array(alpha, delta, fdot, seg=0) -> np.ndarray:
+    alpha, delta, fdot = np.broadcast_arrays(np.asarray(alpha, float), np.asarray(delta, float),
+                                             np.asarray(fdot, float))
+    out = np.zeros(alpha.size, dtype=NODE_DTYPE)
+    out["alpha"] = alpha.ravel()
+    out["delta"] = delta.ravel()
+    out["fdot"] = fdot.ravel()
+    out["seg"] = np.broadcast_to(np.asarray(seg, np.int32), alpha.shape).ravel()
+    return out
+
+
+def _stream_ptr(device: int) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+class Plan:
+    """A plan of fstat_plan: segments on the device, prepared for grid calls."""
+
+    def __init__(self, segments: Sequence[SegmentSpec], det: Detector, eph: Ephemeris,
+                 interp: int = LINEAR_UP2, prec: int = FP32, device: int = 0, max_batch: int = 0):
+        L = lib()
+        self._keep = []
+        segs = (_Segment * len(segments))()
+        for i, s in enumerate(segments):
+            x = np.ascontiguousarray(np.asarray(s.x, dtype=np.float64))
+            self._keep.append(x)
+            segs[i].x = x.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+            segs[i].n = x.size
+            segs[i].dt = float(s.dt)
+            segs[i].n_sidereal_days = int(s.n_days)
+            segs[i].t0 = float(s.t0)
+            if s.mask is not None:
+                m = np.ascontiguousarray(np.asarray(s.mask, dtype=np.uint8))
+                self._keep.append(m)
+                segs[i].mask = m.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+            segs[i].f_ref_hz = float(s.f_ref)
+            segs[i].sigma2 = float(s.sigma2)
+            segs[i].nfft = int(s.nfft)
+        d = _Detector(det.lat, det.lon, det.gamma, det.zeta, det.radius)
+        e = _Ephemeris(eph.obliquity, eph.orbit_radius, eph.orbit_omega, eph.orbit_phase0, eph.sidereal_day,
+                       eph.gmst0)
+        o = _Options(interp, prec, device, max_batch)
+        h = ctypes.c_void_p()
+        _check(L.fstat_plan(segs, len(segments), ctypes.byref(d), ctypes.byref(e), ctypes.byref(o),
+                            ctypes.byref(h)), "fstat_plan")
+        self._keep = None
+        self._h = h
+        self.device = device
+        self.prec = prec
+        self.interp = interp
+        self.nseg = len(segments)
+        self.dtype = torch.float32 if prec == FP32 else torch.float64
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib().fstat_destroy(h)
+            self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self, seg: int = 0) -> dict:
+        n, nfft = ctypes.c_int64(), ctypes.c_int64()
+        s2 = ctypes.c_double()
+        R, C = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().fstat_plan_info(self._h, seg, ctypes.byref(n), ctypes.byref(nfft), ctypes.byref(s2),
+                                     ctypes.byref(R), ctypes.byref(C)), "fstat_plan_info")
+        return dict(n=n.value, nfft=nfft.value, sigma2=s2.value, R=R.value, C=C.value)
+
+    def profile(self, enable: bool = True):
+        """Enable (and reset) or disable per-launch kernel timing."""
+        _check(lib().fstat_profile(self._h, 1 if enable else 0), "fstat_profile")
+
+    def profile_read(self, kind: int) -> dict:
+        """Launch count, summed milliseconds and algorithmic bytes of one kernel kind."""
+        n, ms, b = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
+        _check(lib().fstat_profile_read(self._h, kind, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(b)),
+               "fstat_profile_read")
+        return dict(launches=n.value, ms=ms.value, bytes=b.value)
+
+    def _dev(self):
+        return torch.device("cuda", self.device)
+
+    def _grid(self, nodes: np.ndarray, out: _Out):
+        nodes = np.ascontiguousarray(nodes, dtype=NODE_DTYPE)
+        _check(lib().fstat_grid(self._h, nodes.ctypes.data_as(ctypes.c_void_p), nodes.size, ctypes.byref(out),
+                                _stream_ptr(self.device)), "fstat_grid")
+
+    def grid_map(self, nodes: np.ndarray, k_lo: int, k_hi: int, F: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """F on bins [k_lo, k_hi) of every node: tensor [n_nodes, k_hi - k_lo]."""
+        if F is None:
+            F = torch.empty((len(nodes), k_hi - k_lo), dtype=self.dtype, device=self._dev())
+        out = _Out(mode=OUT_MAP, k_lo=k_lo, k_hi=k_hi, F=F.data_ptr())
+        self._grid(nodes, out)
+        return F
+
+    def grid_max(self, nodes: np.ndarray, k_lo: int, k_hi: int):
+        """Per node: (max F on [k_lo, k_hi), its bin)."""
+        Fmax = torch.empty(len(nodes), dtype=self.dtype, device=self._dev())
+        kmax = torch.empty(len(nodes), dtype=torch.int64, device=self._dev())
+        out = _Out(mode=OUT_MAX, k_lo=k_lo, k_hi=k_hi, Fmax=Fmax.data_ptr(), kmax=kmax.data_ptr())
+        self._grid(nodes, out)
+        return Fmax, kmax
+
+    def grid_crossings(self, nodes: np.ndarray, k_lo: int, k_hi: int, threshold: float, max_crossings: int):
+        """All (node, bin, F) with F > threshold, unordered: a device buffer of
+        fstat_crossing records (int64 [max, 3] words) and the total count."""
+        rec = torch.empty((max(1, max_crossings), 3), dtype=torch.int64, device=self._dev())
+        cnt = torch.empty(1, dtype=torch.int64, device=self._dev())
+        out = _Out(mode=OUT_CROSSINGS, k_lo=k_lo, k_hi=k_hi, threshold=threshold, crossings=rec.data_ptr(),
+                   n_crossings=cnt.data_ptr(), max_crossings=max_crossings)
+        self._grid(nodes, out)
+        return rec, cnt
+
+    @staticmethod
+    def read_crossings(rec: torch.Tensor, cnt: torch.Tensor) -> np.ndarray:
+        """Copy the stored crossings to the host as a CROSSING_DTYPE array."""
+        n = min(int(cnt.cpu().item()), rec.shape[0])
+        return rec[:n].cpu().numpy().view(CROSSING_DTYPE).reshape(-1)
+
+    def demod_series(self, node: np.ndarray) -> torch.Tensor:
+        node = np.ascontiguousarray(np.asarray(node, dtype=NODE_DTYPE).reshape(1))
+        n = self.info(int(node["seg"][0]))["n"]
+        out = torch.empty((n, 4), dtype=torch.float64, device=self._dev())
+        _check(lib().fstat_demod_series(self._h, node.ctypes.data_as(ctypes.c_void_p), _ptr(out),
+                                        _stream_ptr(self.device)), "fstat_demod_series")
+        return out
+
+    # ---- continuous parameters ----
+    def _params(self, params: torch.Tensor, seg: Optional[torch.Tensor]):
+        if params.dtype != torch.float64 or params.device != self._dev() or params.dim() != 2 or params.shape[1] != 4:
+            raise ValueError("params must be a float64 [n, 4] tensor on cuda:%d" % self.device)
+        params = params.contiguous()
+        if seg is not None:
+            seg = seg.to(device=self._dev(), dtype=torch.int32).contiguous()
+        return params, seg
+
+    def eval(self, params: torch.Tensor, seg: Optional[torch.Tensor] = None, want_state: bool = True):
+        params, seg = self._params(params, seg)
+        n = params.shape[0]
+        F = torch.empty(n, dtype=torch.float64, device=self._dev())
+        state = torch.empty((n, STATE), dtype=torch.float64, device=self._dev()) if want_state else None
+        _check(lib().fstat_eval(self._h, _ptr(params), _ptr(seg), n, _ptr(F), _ptr(state),
+                                _stream_ptr(self.device)), "fstat_eval")
+        return F, state
+
+    def adjoint(self, params: torch.Tensor, state: torch.Tensor, gF: Optional[torch.Tensor] = None,
+                seg: Optional[torch.Tensor] = None) -> torch.Tensor:
+        params, seg = self._params(params, seg)
+        n = params.shape[0]
+        dp = torch.empty((n, 4), dtype=torch.float64, device=self._dev())
+        if gF is not None:
+            gF = gF.to(device=self._dev(), dtype=torch.float64).contiguous()
+        _check(lib().fstat_adjoint(self._h, _ptr(params), _ptr(seg), n, _ptr(state.contiguous()), _ptr(gF),
+                                   _ptr(dp), _stream_ptr(self.device)), "fstat_adjoint")
+        return dp
+
+    def grad(self, params: torch.Tensor, seg: Optional[torch.Tensor] = None):
+        params, seg = self._params(params, seg)
+        n = params.shape[0]
+        F = torch.empty(n, dtype=torch.float64, device=self._dev())
+        dF = torch.empty((n, 4), dtype=torch.float64, device=self._dev())
+        _check(lib().fstat_grad(self._h, _ptr(params), _ptr(seg), n, _ptr(F), _ptr(dF),
+                                _stream_ptr(self.device)), "fstat_grad")
+        return F, dF
+
+
+class FStatFn(torch.autograd.Function):
+    """F(params) with params = [n, 4] (f, fdot, alpha, delta); backward runs the
+    adjoint kernel (recomputing the resampled series)."""
+
+    @staticmethod
+    def forward(ctx, params: torch.Tensor, plan: Plan, seg: Optional[torch.Tensor] = None):
+        F, state = plan.eval(params, seg)
+        ctx.plan = plan
+        ctx.seg = seg
+        ctx.save_for_backward(params, state)
+        return F
+
+    @staticmethod
+    def backward(ctx, gF):
+        params, state = ctx.saved_tensors
+        dp = ctx.plan.adjoint(params, state, gF, ctx.seg)
+        return dp, None, None

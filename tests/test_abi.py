@@ -1,0 +1,95 @@
+"""The C-ABI library on the CPU: it loads, exports every entry point the header
+declares, and rejects bad arguments before any device work (no GPU needed)."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1003_0844_amd import fstat
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fstat.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(fstat_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = fstat.lib()
+    names = _declared()
+    assert "fstat_plan" in names and "fstat_grid" in names and "fstat_grad" in names
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(fstat.EXPORTS)
+
+
+def test_strerror():
+    L = fstat.lib()
+    assert L.fstat_strerror(0) == b"ok"
+    assert b"sidereal" in L.fstat_strerror(-2)
+    assert L.fstat_strerror(-99) == b"unknown status"
+
+
+def _plan_status(n=43082, dt=2.0, days=1, nfft=0, interp=1, prec=0, x=None, det=None):
+    L = fstat.lib()
+    x = np.zeros(n) if x is None else x
+    seg = fstat._Segment()
+    seg.x = x.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    seg.n, seg.dt, seg.n_sidereal_days, seg.f_ref_hz, seg.sigma2, seg.nfft = n, dt, days, 435.1875, 1.0, nfft
+    d = det or fstat.default_detector()
+    dd = fstat._Detector(d.lat, d.lon, d.gamma, d.zeta, d.radius)
+    e = fstat.Ephemeris()
+    ee = fstat._Ephemeris(e.obliquity, e.orbit_radius, e.orbit_omega, e.orbit_phase0, e.sidereal_day, e.gmst0)
+    o = fstat._Options(interp, prec, 0, 0)
+    h = ctypes.c_void_p()
+    return L.fstat_plan(ctypes.byref(seg), 1, ctypes.byref(dd), ctypes.byref(ee), ctypes.byref(o), ctypes.byref(h))
+
+
+def test_plan_rejects_non_integer_sidereal_days():
+    assert _plan_status(n=43000) == fstat.ENOTINTDAYS
+    assert _plan_status(n=43082, days=2) == fstat.ENOTINTDAYS
+
+
+def test_plan_rejects_bad_sizes():
+    assert _plan_status(nfft=3 << 14) == fstat.EUNSUPPORTED        # not a power of two
+    assert _plan_status(nfft=1 << 15) == fstat.EUNSUPPORTED        # below n
+    assert _plan_status(nfft=1 << 23) == fstat.EUNSUPPORTED        # above 2^22
+    assert _plan_status(n=8, dt=86164.0 / 8) == fstat.EUNSUPPORTED  # n < 16
+
+
+def test_plan_rejects_bad_values():
+    assert _plan_status(interp=3) == fstat.EINVAL
+    assert _plan_status(prec=2) == fstat.EINVAL
+    x = np.zeros(43082)
+    x[7] = math.nan
+    assert _plan_status(x=x) == fstat.EINVAL
+    assert _plan_status(dt=-2.0) == fstat.EINVAL
+    L = fstat.lib()
+    h = ctypes.c_void_p()
+    assert L.fstat_plan(None, 1, None, None, None, ctypes.byref(h)) == fstat.EINVAL
+
+
+def test_calls_on_null_plan_are_rejected():
+    L = fstat.lib()
+    nodes = fstat.nodes_array([0.0], [0.0], [0.0])
+    out = fstat._Out(mode=0, k_lo=0, k_hi=10, F=1)
+    assert L.fstat_grid(None, nodes.ctypes.data_as(ctypes.c_void_p), 1, ctypes.byref(out), None) == fstat.EINVAL
+    assert L.fstat_eval(None, None, None, 1, None, None, None) == fstat.EINVAL
+    assert L.fstat_grad(None, None, None, 1, None, None, None) == fstat.EINVAL
+    assert L.fstat_adjoint(None, None, None, 1, None, None, None, None) == fstat.EINVAL
+    assert L.fstat_plan_info(None, 0, None, None, None, None, None) == fstat.EINVAL
+    L.fstat_destroy(None)
+
+
+def test_node_record_layout_matches_header():
+    # fstat_node: 3 doubles, 2 int32 = 32 bytes; fstat_crossing: 24 bytes
+    assert fstat.NODE_DTYPE.itemsize == 32
+    assert fstat.CROSSING_DTYPE.itemsize == 24
+    assert ctypes.sizeof(fstat._Segment) == 72
+    assert ctypes.sizeof(fstat._Out) == 80

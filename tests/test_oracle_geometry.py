@@ -178,3 +178,18 @@ def test_earth_rotation_rate_matches_paper():
     # rate corresponds to 86164.0989 s -- within 1.2e-6 relative
     w = 2 * math.pi / EPH.sidereal_day
     assert abs(w / gold["earth_rotation_rate"]["value"] - 1) < 1.2e-6
+
+
+def test_extended_precision_delay_matches_matrix_form():
+    # the extended-precision copy used for the f_ref phi_m phase
+    T = RNG.uniform(0, 3.2e7, 20)
+    for _ in range(5):
+        al, de = RNG.uniform(0, 2 * math.pi), math.asin(RNG.uniform(-1, 1))
+        got = model.roemer_delay_ext(T, al, de, DET, EPH)
+        assert got.dtype == np.longdouble
+        assert np.max(np.abs(got.astype(np.float64) - _roemer_matrix_route(T, al, de, DET, EPH))) < 1e-10
+        # and it resolves differences FP64 cannot: relative to phi_m(0) the
+        # two agree to the FP64 rounding of a ~500 s quantity
+        d_ext = (got - model.roemer_delay_ext(0.0, al, de, DET, EPH)).astype(np.float64)
+        d_64 = model.roemer_delay(T, al, de, DET, EPH) - model.roemer_delay(0.0, al, de, DET, EPH)
+        assert np.max(np.abs(d_ext - d_64)) < 1e-12

@@ -87,8 +87,11 @@ def test_wrong_ssb_grid_origin_is_caught(monkeypatch):
 
 
 def test_wrong_sign_of_spindown_doppler_term_is_caught(monkeypatch):
-    def bad(t, pm, f_ref, fdot):
-        return f_ref * pm + fdot * (0.5 * t * t - pm * t)
+    def bad(t, T0, alpha, delta, f_ref, fdot, det, eph):
+        pm = model.roemer_delay(T0 + t, alpha, delta, det, eph)
+        pm0 = model.roemer_delay(T0, alpha, delta, det, eph)
+        cyc = f_ref * (pm - pm0) + fdot * (0.5 * t * t - pm * t)
+        return cyc - np.round(cyc)
     monkeypatch.setattr(method, "demod_cycles", bad)
     # visible once the spindown is large enough for its Doppler term to matter
     dt = 13.0

@@ -80,14 +80,15 @@ def test_periodic_spline_matches_library():
 def test_linear_and_nearest_interpolation():
     seg = small_segment(days=1, dt=26.0)
     y, _ = method._upsampled(seg, method.LINEAR_UP2)
-    u = np.array([0.0, 0.25, 0.5, 10.75, seg.n - 1.0, -1e-9, seg.n - 1 + 1e-9])
+    u = np.array([0.0, 0.25, 0.5, 10.75, seg.n - 1.0, -1e-5, seg.n - 1 + 1e-5, -1e-9, seg.n - 1 + 1e-9])
     xr, _ = method.interpolate(seg, u, method.LINEAR_UP2)
     assert xr[0] == y[0] and xr[4] == y[2 * seg.n - 2]
     assert abs(xr[0] - seg.x[0]) < 1e-13 and abs(xr[4] - seg.x[-1]) < 1e-13
     assert abs(xr[1] - 0.5 * (y[0] + y[1])) < 1e-15
     assert xr[2] == y[1]
     assert abs(xr[3] - 0.5 * (y[21] + y[22])) < 1e-15
-    assert xr[5] == 0.0 and xr[6] == 0.0
+    assert xr[5] == 0.0 and xr[6] == 0.0              # outside the span
+    assert xr[7] == y[0] and xr[8] == y[2 * seg.n - 2]  # within the margin: clamped
     xn, _ = method.interpolate(seg, np.array([0.49, 0.5, 1.49, seg.n - 1.0]), method.NEAREST)
     assert list(xn) == [seg.x[0], seg.x[1], seg.x[1], seg.x[-1]]
 

@@ -35,7 +35,38 @@ def parse():
     ap.add_argument("--plain-nodes", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--counters", action="store_true",
+                    help="short run for hardware-counter collection: one grid call on the first 64 nodes "
+                         "and a 1 GiB device copy of known size (the calibration of the byte counters)")
     return ap.parse_args()
+
+
+def counters_run(args):
+    """One grid call on 4 sky positions x 16 spindowns, then a plain copy of
+    exactly 2^30 bytes: the copy's FETCH_SIZE / WRITE_SIZE readings give the
+    scale from counter units to bytes moved."""
+    import torch
+    from paper_1003_0844_amd import fstat
+    w, x, nodes = workload()
+    sub = nodes[:64]
+    plan = fstat.Plan([fstat.SegmentSpec(x=x, dt=w.dt, n_days=w.days, nfft=w.nfft)], fstat.default_detector(),
+                      fstat.Ephemeris(), interp=fstat.LINEAR_UP2, prec=fstat.FP32, max_batch=args.max_batch)
+    F = torch.empty((len(sub), w.nfft // 2), dtype=torch.float32, device="cuda")
+    plan.grid_map(sub, 0, w.nfft // 2, F)
+    torch.cuda.synchronize()
+    src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    ev[0].record()
+    dst.copy_(src)
+    ev[1].record()
+    torch.cuda.synchronize()
+    ms = ev[0].elapsed_time(ev[1])
+    print(json.dumps({"counters_run": "done", "grid_nodes": len(sub), "copy_bytes_each_way": 1 << 30,
+                      "copy_ms": round(ms, 4), "copy_GBps_read_plus_write": round(2 * (1 << 30) / ms / 1e6, 1)}),
+          flush=True)
 
 
 def log(*a):
@@ -82,6 +113,9 @@ def main():
         print("bench.py runs on exactly one GPU: the F-statistic grid shards over sky positions, "
               "but this build measures one GPU's share only (--gpus 1).", file=sys.stderr)
         sys.exit(2)
+    if args.counters:
+        counters_run(args)
+        return
     import numpy as np
     import torch
     from paper_1003_0844_amd import fstat
@@ -89,9 +123,12 @@ def main():
     w, x, nodes = workload()
     nn = len(nodes)
     half = w.nfft // 2
-    log("workload: %s; building plan" % w.name)
+    log("workload: %s; building plan (autotuned)" % w.name)
     plan = fstat.Plan([fstat.SegmentSpec(x=x, dt=w.dt, n_days=w.days, nfft=w.nfft)], fstat.default_detector(),
-                      fstat.Ephemeris(), interp=fstat.LINEAR_UP2, prec=fstat.FP32, max_batch=args.max_batch)
+                      fstat.Ephemeris(), interp=fstat.LINEAR_UP2, prec=fstat.FP32, max_batch=args.max_batch,
+                      autotune=True)
+    sched = plan.schedule()
+    log("schedule: %s" % sched)
     F = torch.empty((nn, half), dtype=torch.float32, device="cuda")
     for i in range(args.warmup):
         plan.grid_map(nodes, 0, half, F)
@@ -117,6 +154,9 @@ def main():
                           "GBps": prof[k]["bytes"] / max(1e-12, prof[k]["ms"] * 1e-3) / 1e9} for k in names}
     step_ms = 1e3 * el / args.steps
     value = nn * args.steps / el
+    # whole-path roofline: algorithmic bytes of every kernel of a step over the step time
+    step_bytes = sum(prof[k]["bytes"] for k in names) / args.steps
+    path_gbs = step_bytes / (el / args.steps) / 1e9
 
     # the plain path: all-FP64, one node per launch, on the first nodes of the grid
     sub = nodes[:args.plain_nodes]
@@ -143,8 +183,11 @@ def main():
                    "nodes": nn, "n": w.n, "dt": w.dt, "nfft": w.nfft, "phase": "f64"},
         "roofline": {"bound": "hbm", "kernel": names[dom], "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "avg_launch_us": round(1e3 * avg_ms, 2), "bytes_per_launch": bytes_per_launch},
+                     "avg_launch_us": round(1e3 * avg_ms, 2), "bytes_per_launch": bytes_per_launch,
+                     "path_GBps": round(path_gbs, 1), "path_frac": round(path_gbs / HBM_PEAK_GBS, 4),
+                     "path_bytes_per_node": round(step_bytes / nn)},
         "kernels": kernels,
+        "schedule": sched,
         "plain_fp64_one_node_per_launch": {"value": round(plain, 1), "unit": "nodes/s",
                                            "nodes": len(sub), "speedup": round(value / plain, 2)},
         "f32_vs_f64_max_rel_err": err32,

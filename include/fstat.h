@@ -108,7 +108,13 @@ typedef struct {
   int32_t interp;    /* FSTAT_NEAREST / FSTAT_LINEAR_UP2 / FSTAT_CUBIC_UP2 */
   int32_t prec;      /* FSTAT_FP32 / FSTAT_FP64 */
   int32_t device;    /* HIP device ordinal */
-  int32_t max_batch; /* nodes per FFT batch; 0 = library default */
+  int32_t max_batch; /* nodes per FFT batch; 0 = library default (or the tuned value) */
+  int32_t autotune;  /* 1: at plan time, time the candidate FFT splits nfft = R x C
+                        (C = 1024, 2048, 4096 columns where valid) and node-batch sizes
+                        (8, 16, 32) of every segment on a sample grid and keep the
+                        fastest; the choice is cached in the file named by the
+                        environment variable FSTAT_TUNE_CACHE if it is set.
+                        0: fixed defaults. */
 } fstat_options;
 
 typedef struct fstat_plan_s *fstat_plan_t;
@@ -193,6 +199,11 @@ fstat_status fstat_grad(fstat_plan_t p, const double *params, const int32_t *seg
 /* Plan facts.  Host outputs; any pointer may be NULL. */
 fstat_status fstat_plan_info(fstat_plan_t p, int32_t seg, int64_t *n, int64_t *nfft, double *sigma2,
                              int32_t *fft_R, int32_t *fft_C);
+
+/* The schedule in use for a segment (defaults or autotuned): FFT split
+ * nfft = R x C, columns per second-pass workgroup B2, nodes per batch. */
+fstat_status fstat_plan_schedule(fstat_plan_t p, int32_t seg, int32_t *R, int32_t *C, int32_t *B2,
+                                 int32_t *batch);
 
 /* Diagnostic: the demodulated, resampled, a/b-weighted series z_a, z_b of one
  * node (the input of the FFTs, natural order), as FP64 device [n][4] =

@@ -3,6 +3,8 @@
 // method runs in the kernels of sky.hip, grid.hip, prep.hip and grad.hip.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -18,6 +20,7 @@ constexpr double TWO_PI = 6.283185307179586476925286766559;
 struct SegPlan {
   SegDev dev{};
   int B2 = 0;
+  int node_cap = 16;  // nodes per FFT batch
   void* twC = nullptr;
   void* twR = nullptr;
   void* twlo = nullptr;
@@ -63,6 +66,9 @@ struct fstat_plan_s {
   size_t pinned_bytes = 0;
   hipEvent_t staged = nullptr;
   bool staged_pending = false;
+  hipStream_t side = nullptr;  // second stream of the grid pipeline (default priority)
+  hipEvent_t ev_p1[2] = {nullptr, nullptr}, ev_p2[2] = {nullptr, nullptr}, ev_sky[2] = {nullptr, nullptr};
+  hipEvent_t ev_join = nullptr;
 };
 
 namespace {
@@ -101,6 +107,28 @@ void choose_split(int prec, int64_t nfft, int& R, int& C) {
 
 size_t elem_real(int prec) { return prec == 0 ? 4 : 8; }
 
+// FFT split of a segment: first pass over R columns of length C, second pass
+// over length R in blocks of B2 columns.
+void apply_split(SegPlan& sp, int prec, int C) {
+  SegDev& d = sp.dev;
+  d.C = C;
+  d.R = (int)(d.nfft / C);
+  d.Ceff = (int)((d.n + d.R - 1) / d.R);
+  sp.B2 = fsk::pass2_b2(prec, d.R);
+}
+
+bool split_valid(int prec, int64_t nfft, int C) {
+  const int64_t R = nfft / C;
+  const int64_t cmax = prec == 0 ? 4096 : 4096;
+  return C >= 64 && C <= cmax && R >= 16 && R <= 1024 && (int64_t)C * R == nfft;
+}
+
+hipError_t make_split_tables(const SegPlan& sp, int prec, hipStream_t st) {
+  hipError_t e = fsk::make_twiddles(prec, sp.dev.C, sp.dev.C, 1, sp.twC, st);
+  if (e == hipSuccess) e = fsk::make_twiddles(prec, sp.dev.R, sp.dev.R, 1, sp.twR, st);
+  return e;
+}
+
 void free_seg(SegPlan& s) {
   void* ptrs[] = {s.twC, s.twR, s.twlo, s.twhi, s.x, s.xf, s.y, s.yf, s.M, s.Mf, s.mask};
   for (void* p : ptrs)
@@ -119,6 +147,9 @@ void destroy_plan(fstat_plan_s* p) {
   if (p->ws) (void)hipFree(p->ws);
   if (p->pinned) (void)hipHostFree(p->pinned);
   if (p->staged) (void)hipEventDestroy(p->staged);
+  for (hipEvent_t ev : {p->ev_p1[0], p->ev_p1[1], p->ev_p2[0], p->ev_p2[1], p->ev_sky[0], p->ev_sky[1], p->ev_join})
+    if (ev) (void)hipEventDestroy(ev);
+  if (p->side) (void)hipStreamDestroy(p->side);
   for (auto* v : {&p->prof.pending, &p->prof.pool})
     for (auto& pr : *v) {
       (void)hipEventDestroy(pr.a);
@@ -185,11 +216,8 @@ fstat_status build_segment(const fstat_segment& s, const fstat_detector& det, co
   d.nfft = nfft;
   int R, C;
   choose_split(prec, nfft, R, C);
-  d.R = R;
-  d.C = C;
-  d.Ceff = (int)((n + R - 1) / R);
+  apply_split(sp, prec, C);
   d.interp = interp;
-  sp.B2 = fsk::pass2_b2(prec, R);
 
   const size_t er = elem_real(prec);
   double* xraw = nullptr;
@@ -235,12 +263,12 @@ fstat_status build_segment(const fstat_segment& s, const fstat_detector& det, co
     // twiddle tables in the working precision
     const int64_t nlo = nfft < 4096 ? nfft : 4096;
     const int64_t nhi = nfft / 4096 > 1 ? nfft / 4096 : 1;
-    if ((e = hipMalloc(&sp.twC, C * 2 * er)) != hipSuccess) break;
-    if ((e = hipMalloc(&sp.twR, R * 2 * er)) != hipSuccess) break;
+    // (room for every split the tuner may choose: C <= 4096, R <= 1024)
+    if ((e = hipMalloc(&sp.twC, 4096 * 2 * er)) != hipSuccess) break;
+    if ((e = hipMalloc(&sp.twR, 1024 * 2 * er)) != hipSuccess) break;
     if ((e = hipMalloc(&sp.twlo, 4096 * 2 * er)) != hipSuccess) break;
     if ((e = hipMalloc(&sp.twhi, nhi * 2 * er)) != hipSuccess) break;
-    if ((e = fsk::make_twiddles(prec, C, C, 1, sp.twC, nullptr)) != hipSuccess) break;
-    if ((e = fsk::make_twiddles(prec, R, R, 1, sp.twR, nullptr)) != hipSuccess) break;
+    if ((e = make_split_tables(sp, prec, nullptr)) != hipSuccess) break;
     if ((e = fsk::make_twiddles(prec, nfft, nlo, 1, sp.twlo, nullptr)) != hipSuccess) break;
     if ((e = fsk::make_twiddles(prec, nfft, nhi, 4096, sp.twhi, nullptr)) != hipSuccess) break;
     if ((e = hipDeviceSynchronize()) != hipSuccess) break;
@@ -336,101 +364,9 @@ struct SkyBatch {
 
 }  // namespace
 
-// ===========================================================================
-extern "C" {
-
-const char* fstat_strerror(fstat_status s) {
-  switch (s) {
-    case FSTAT_OK: return "ok";
-    case FSTAT_EINVAL: return "invalid argument";
-    case FSTAT_ENOTINTDAYS: return "observation time is not a whole number of sidereal days";
-    case FSTAT_ENOMEM: return "out of memory";
-    case FSTAT_EDEVICE: return "HIP device error";
-    case FSTAT_EUNSUPPORTED: return "unsupported size";
-    default: return "unknown status";
-  }
-}
-
-fstat_status fstat_plan(const fstat_segment* segs, int32_t nseg, const fstat_detector* det,
-                        const fstat_ephemeris* eph, const fstat_options* opt, fstat_plan_t* out) {
-  if (!segs || nseg <= 0 || !det || !eph || !opt || !out) return FSTAT_EINVAL;
-  if (opt->interp < 0 || opt->interp > 2 || opt->prec < 0 || opt->prec > 1 || opt->max_batch < 0)
-    return FSTAT_EINVAL;
-  if (!(eph->sidereal_day_s > 0.0) || !std::isfinite(eph->orbit_radius_m) || !std::isfinite(eph->orbit_omega) ||
-      !std::isfinite(det->radius_m) || !std::isfinite(det->lat_rad))
-    return FSTAT_EINVAL;
-  for (int i = 0; i < nseg; ++i) {
-    fstat_status v = validate_segment(segs[i], *eph, opt->prec);
-    if (v != FSTAT_OK) return v;
-  }
-  int ndev = 0;
-  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return FSTAT_EDEVICE;
-  if (opt->device < 0 || opt->device >= ndev) return FSTAT_EINVAL;
-  DeviceGuard guard(opt->device);
-  if (!guard.ok) return FSTAT_EDEVICE;
-
-  fstat_plan_s* p = new (std::nothrow) fstat_plan_s();
-  if (!p) return FSTAT_ENOMEM;
-  p->device = opt->device;
-  p->interp = opt->interp;
-  p->prec = opt->prec;
-  p->max_batch = opt->max_batch;
-  p->segs.resize(nseg);
-  for (int i = 0; i < nseg; ++i) {
-    fstat_status rc = build_segment(segs[i], *det, *eph, opt->prec, opt->interp, p->segs[i]);
-    if (rc != FSTAT_OK) {
-      destroy_plan(p);
-      return rc;
-    }
-  }
-  std::vector<SegDev> hs(nseg);
-  for (int i = 0; i < nseg; ++i) hs[i] = p->segs[i].dev;
-  hipError_t e = hipMalloc(&p->d_segs, nseg * sizeof(SegDev));
-  if (e == hipSuccess) e = hipMemcpy(p->d_segs, hs.data(), nseg * sizeof(SegDev), hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&p->staged, hipEventDisableTiming);
-  if (e != hipSuccess) {
-    destroy_plan(p);
-    return from_hip(e);
-  }
-  *out = p;
-  return FSTAT_OK;
-}
-
-void fstat_destroy(fstat_plan_t p) { destroy_plan(p); }
-
-fstat_status fstat_plan_info(fstat_plan_t p, int32_t seg, int64_t* n, int64_t* nfft, double* sigma2, int32_t* R,
-                             int32_t* C) {
-  if (!p || seg < 0 || seg >= (int32_t)p->segs.size()) return FSTAT_EINVAL;
-  const SegDev& d = p->segs[seg].dev;
-  if (n) *n = d.n;
-  if (nfft) *nfft = d.nfft;
-  if (sigma2) *sigma2 = d.sigma2;
-  if (R) *R = d.R;
-  if (C) *C = d.C;
-  return FSTAT_OK;
-}
-
-fstat_status fstat_grid(fstat_plan_t p, const fstat_node* nodes, int64_t n_nodes, const fstat_out* out,
-                        void* hip_stream) {
-  if (!p || !nodes || n_nodes <= 0 || !out) return FSTAT_EINVAL;
-  if (n_nodes > (int64_t)INT32_MAX) return FSTAT_EUNSUPPORTED;
-  if (out->mode < 0 || out->mode > 2) return FSTAT_EINVAL;
-  if (out->k_lo < 0 || out->k_hi <= out->k_lo) return FSTAT_EINVAL;
-  if (out->mode == 0 && !out->F) return FSTAT_EINVAL;
-  if (out->mode == 1 && (!out->Fmax || !out->kmax)) return FSTAT_EINVAL;
-  if (out->mode == 2 && (!out->n_crossings || (out->max_crossings > 0 && !out->crossings) || out->max_crossings < 0))
-    return FSTAT_EINVAL;
-  const int nseg = (int)p->segs.size();
-  for (int64_t i = 0; i < n_nodes; ++i) {
-    const fstat_node& nd = nodes[i];
-    if (nd.seg < 0 || nd.seg >= nseg || !std::isfinite(nd.alpha) || !std::isfinite(nd.delta) ||
-        !std::isfinite(nd.fdot))
-      return FSTAT_EINVAL;
-    if (out->k_hi > p->segs[nd.seg].dev.nfft / 2) return FSTAT_EINVAL;
-  }
-  DeviceGuard guard(p->device);
-  if (!guard.ok) return FSTAT_EDEVICE;
-  hipStream_t st = (hipStream_t)hip_stream;
+// The launch sequence of a grid call (arguments already validated).
+fstat_status run_grid(fstat_plan_s* p, const fstat_node* nodes, int64_t n_nodes, const fstat_out* out,
+                      hipStream_t st) {
   const int prec = p->prec;
 
   // ---- group nodes: by segment, then by sky position ----
@@ -474,22 +410,23 @@ fstat_status fstat_grid(fstat_plan_t p, const fstat_node* nodes, int64_t n_nodes
       batches.push_back(b);
     }
   }
-  // workspace: descriptors + per-batch sky data + spill + partials
-  int node_cap = p->max_batch > 0 ? p->max_batch : (prec == 0 ? 16 : 4);
+  // workspace: descriptors; two sets of sky data (one per sky-batch parity);
+  // two spill buffers (one per node-chunk parity); max partials
   size_t max_quads = 0, max_spill = 0, max_part = 0, max_abc = 0;
   int max_sky = 0;
   for (const auto& b : batches) {
     const SegPlan& sp = p->segs[b.seg];
     const SegDev& d = sp.dev;
     max_quads = std::max(max_quads, (size_t)b.nsky * d.R * d.Ceff * 4 * elem_real(prec));
-    max_spill = std::max(max_spill, (size_t)node_cap * d.nfft * 4 * elem_real(prec));
-    max_part = std::max(max_part, (size_t)node_cap * (d.C / sp.B2) * sizeof(MaxPartial));
+    max_spill = std::max(max_spill, (size_t)sp.node_cap * d.nfft * 4 * elem_real(prec));
+    max_part = std::max(max_part, (size_t)sp.node_cap * (d.C / sp.B2) * sizeof(MaxPartial));
     max_abc = std::max(max_abc, (size_t)b.nsky * fsk::sky_prep_blocks(d) * 3 * sizeof(double));
     max_sky = std::max(max_sky, b.nsky);
   }
   const size_t desc_bytes = align_up(sky_ad.size() * sizeof(double)) + align_up(ndev.size() * sizeof(NodeDev));
-  need_ws = desc_bytes + align_up(max_quads) + align_up(max_spill) + align_up(max_part) + align_up(max_abc) +
-            align_up(max_sky * sizeof(SkyConst)) + align_up(max_sky * sizeof(SkyCoef)) + 4096;
+  const size_t set_bytes = align_up(max_quads) + align_up(max_abc + 8) + align_up(max_sky * sizeof(SkyConst)) +
+                           align_up(max_sky * sizeof(SkyCoef));
+  need_ws = desc_bytes + 2 * set_bytes + 2 * align_up(max_spill) + align_up(max_part + 16) + 4096;
   fstat_status rc = ensure_ws(p, need_ws);
   if (rc != FSTAT_OK) return rc;
   rc = ensure_pinned(p, desc_bytes);
@@ -497,12 +434,22 @@ fstat_status fstat_grid(fstat_plan_t p, const fstat_node* nodes, int64_t n_nodes
   Carve cv{(char*)p->ws};
   double* d_ad = cv.take<double>(sky_ad.size());
   NodeDev* d_nodes = cv.take<NodeDev>(ndev.size());
-  void* d_quads = cv.take<char>(max_quads);
-  void* d_spill = cv.take<char>(max_spill);
+  struct SkySet {
+    void* quads;
+    double* abc;
+    SkyConst* sky;
+    SkyCoef* coef;
+  } sets[2];
+  for (auto& ss : sets) {
+    ss.quads = cv.take<char>(max_quads);
+    ss.abc = cv.take<double>(max_abc / sizeof(double) + 1);
+    ss.sky = cv.take<SkyConst>(max_sky);
+    ss.coef = cv.take<SkyCoef>(max_sky);
+  }
+  void* d_spill[2];
+  d_spill[0] = cv.take<char>(max_spill);
+  d_spill[1] = cv.take<char>(max_spill);
   MaxPartial* d_part = cv.take<MaxPartial>(max_part / sizeof(MaxPartial) + 1);
-  double* d_abc = cv.take<double>(max_abc / sizeof(double) + 1);
-  SkyConst* d_sky = cv.take<SkyConst>(max_sky);
-  SkyCoef* d_coef = cv.take<SkyCoef>(max_sky);
   // stage descriptors
   char* hp = (char*)p->pinned;
   std::memcpy(hp, sky_ad.data(), sky_ad.size() * sizeof(double));
@@ -524,35 +471,309 @@ fstat_status fstat_grid(fstat_plan_t p, const fstat_node* nodes, int64_t n_nodes
   go.max_xing = out->max_crossings;
   if (out->mode == 2) HIP_TRY(fsk::zero_u64(out->n_crossings, st));
 
+  // Two-stream pipeline: the sky preparation and the first FFT pass run on the
+  // caller's stream, the second pass on the plan's side stream, so that pass 1
+  // of chunk c+1 (arithmetic-bound) overlaps pass 2 of chunk c (memory-bound).
+  // Chunk c uses spill buffer c % 2; sky batch s uses sky set s % 2.
+  hipStream_t s2 = p->side;
   const double er = (double)elem_real(prec);
+  int64_t chunk = 0;
+  int sbi = 0;
   for (const auto& b : batches) {
     const SegPlan& sp = p->segs[b.seg];
     const SegDev& d = sp.dev;
+    const SkySet& ss = sets[sbi % 2];
     const int nblk = fsk::sky_prep_blocks(d);
     const int64_t qstride = (int64_t)d.R * d.Ceff;
     const double rec_bytes = 4.0 * er * (double)qstride;  // one sky record
-    HIP_TRY(timed(p, FSTAT_K_OTHER, 0.0, st, [&] { return fsk::sky_setup(d_ad + 2 * b.sky0, b.nsky, d, d_sky, st); }));
+    if (sbi >= 2) HIP_TRY(hipStreamWaitEvent(st, p->ev_sky[sbi % 2], 0));
+    HIP_TRY(timed(p, FSTAT_K_OTHER, 0.0, st, [&] { return fsk::sky_setup(d_ad + 2 * b.sky0, b.nsky, d, ss.sky, st); }));
     HIP_TRY(timed(p, FSTAT_K_SKY, rec_bytes * b.nsky, st, [&] {
-      return fsk::sky_prep(prec, d, d_sky, b.nsky, d_quads, qstride, d_abc, nblk, st);
+      return fsk::sky_prep(prec, d, ss.sky, b.nsky, ss.quads, qstride, ss.abc, nblk, st);
     }));
-    HIP_TRY(timed(p, FSTAT_K_OTHER, 0.0, st, [&] { return fsk::sky_finalize(d, d_abc, nblk, b.nsky, d_coef, st); }));
-    for (int n0 = 0; n0 < b.nnode; n0 += node_cap) {
+    HIP_TRY(timed(p, FSTAT_K_OTHER, 0.0, st, [&] { return fsk::sky_finalize(d, ss.abc, nblk, b.nsky, ss.coef, st); }));
+    const int node_cap = sp.node_cap;
+    for (int n0 = 0; n0 < b.nnode; n0 += node_cap, ++chunk) {
       const int nn = std::min(node_cap, b.nnode - n0);
       const NodeDev* dn = d_nodes + b.node0 + n0;
-      const double spill = 4.0 * er * (double)d.nfft * nn;
+      void* spill = d_spill[chunk % 2];
+      const double sbytes = 4.0 * er * (double)d.nfft * nn;
       const double outb = out->mode == 0 ? er * (double)(out->k_hi - out->k_lo) * nn : 0.0;
-      HIP_TRY(timed(p, FSTAT_K_PASS1, spill + rec_bytes * nn / std::max(1, b.nnode / b.nsky), st, [&] {
-        return fsk::grid_pass1(prec, d.C, d, d_quads, qstride, d_sky, dn, nn, sp.twC, sp.twlo, sp.twhi, d_spill, st);
+      if (chunk >= 2) HIP_TRY(hipStreamWaitEvent(st, p->ev_p2[chunk % 2], 0));
+      HIP_TRY(timed(p, FSTAT_K_PASS1, sbytes + rec_bytes * nn / std::max(1, b.nnode / b.nsky), st, [&] {
+        return fsk::grid_pass1(prec, d.C, d, ss.quads, qstride, ss.sky, dn, nn, sp.twC, sp.twlo, sp.twhi, spill, st);
       }));
-      HIP_TRY(timed(p, FSTAT_K_PASS2, spill + outb, st, [&] {
-        return fsk::grid_pass2(prec, d.R, sp.B2, d, d_spill, dn, nn, d_coef, sp.twR, go, d_part, st);
+      HIP_TRY(hipEventRecord(p->ev_p1[chunk % 2], st));
+      HIP_TRY(hipStreamWaitEvent(s2, p->ev_p1[chunk % 2], 0));
+      HIP_TRY(timed(p, FSTAT_K_PASS2, sbytes + outb, s2, [&] {
+        return fsk::grid_pass2(prec, d.R, sp.B2, d, spill, dn, nn, ss.coef, sp.twR, go, d_part, s2);
       }));
       if (out->mode == 1)
-        HIP_TRY(timed(p, FSTAT_K_OTHER, 0.0, st,
-                      [&] { return fsk::max_finalize(d_part, d.C / sp.B2, dn, nn, prec, go, st); }));
+        HIP_TRY(timed(p, FSTAT_K_OTHER, 0.0, s2,
+                      [&] { return fsk::max_finalize(d_part, d.C / sp.B2, dn, nn, prec, go, s2); }));
+      HIP_TRY(hipEventRecord(p->ev_p2[chunk % 2], s2));
+    }
+    HIP_TRY(hipEventRecord(p->ev_sky[sbi % 2], s2));  // sky set free once its last pass 2 is done
+    ++sbi;
+  }
+  HIP_TRY(hipEventRecord(p->ev_join, s2));
+  HIP_TRY(hipStreamWaitEvent(st, p->ev_join, 0));
+  return FSTAT_OK;
+}
+
+
+// ---------------------------------------------------------------------------
+// autotuner: FFT split and node-batch size per segment
+// ---------------------------------------------------------------------------
+struct TuneKey {
+  int prec, interp;
+  int64_t nfft, n;
+};
+
+bool cache_lookup(const TuneKey& k, int& C, int& batch) {
+  const char* path = std::getenv("FSTAT_TUNE_CACHE");
+  if (!path || !*path) return false;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return false;
+  char line[256];
+  bool found = false;
+  while (std::fgets(line, sizeof line, f)) {
+    int pr, ip, c, b;
+    long long nf, nn;
+    if (std::sscanf(line, "fstat-tune-v1 %d %d %lld %lld %d %d", &pr, &ip, &nf, &nn, &c, &b) == 6 && pr == k.prec &&
+        ip == k.interp && nf == k.nfft && nn == k.n) {
+      C = c;
+      batch = b;
+      found = true;  // the last matching line wins
     }
   }
+  std::fclose(f);
+  return found;
+}
+
+void cache_store(const TuneKey& k, int C, int batch) {
+  const char* path = std::getenv("FSTAT_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE* f = std::fopen(path, "a");
+  if (!f) return;
+  std::fprintf(f, "fstat-tune-v1 %d %d %lld %lld %d %d\n", k.prec, k.interp, (long long)k.nfft, (long long)k.n, C,
+               batch);
+  std::fclose(f);
+}
+
+// Times every valid (C, batch) on a 4-sky x 16-spindown sample of the segment
+// (full map into a scratch buffer, two timed runs each, the faster counts)
+// and keeps the fastest.
+fstat_status tune_segment(fstat_plan_s* p, int si) {
+  SegPlan& sp = p->segs[si];
+  const int prec = p->prec;
+  const int64_t nfft = sp.dev.nfft;
+  const TuneKey key{prec, p->interp, nfft, sp.dev.n};
+  int C = sp.dev.C, batch = sp.node_cap;
+  if (cache_lookup(key, C, batch) && split_valid(prec, nfft, C) && batch > 0) {
+    apply_split(sp, prec, C);
+    sp.node_cap = batch;
+    HIP_TRY(make_split_tables(sp, prec, nullptr));
+    HIP_TRY(hipDeviceSynchronize());
+    return FSTAT_OK;
+  }
+  std::vector<int> cands;
+  for (int c : {1024, 2048, 4096, sp.dev.C})
+    if (split_valid(prec, nfft, c) && std::find(cands.begin(), cands.end(), c) == cands.end()) cands.push_back(c);
+  std::vector<int> batches;
+  if (p->max_batch > 0) batches = {p->max_batch};
+  else if (prec == 0) batches = {8, 16, 32};
+  else batches = {2, 4, 8};
+  const int nsky = 4, nfd = 16;
+  std::vector<fstat_node> nodes(nsky * nfd);
+  for (int s = 0; s < nsky; ++s)
+    for (int f = 0; f < nfd; ++f) {
+      fstat_node& nd = nodes[s * nfd + f];
+      nd.alpha = 0.4 + 1.5 * s;
+      nd.delta = -0.9 + 0.6 * s;
+      nd.fdot = -1e-9 * f / (nfd - 1);
+      nd.seg = si;
+      nd.pad = 0;
+    }
+  const int64_t kh = nfft / 2;
+  void* scratch = nullptr;
+  hipStream_t st = nullptr;
+  hipEvent_t ea = nullptr, eb = nullptr;
+  fstat_status rc = FSTAT_OK;
+  double best_ms = 1e300;
+  int best_C = sp.dev.C, best_b = sp.node_cap;
+  hipError_t e = hipMalloc(&scratch, (size_t)nodes.size() * kh * elem_real(prec));
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreate(&ea);
+  if (e == hipSuccess) e = hipEventCreate(&eb);
+  if (e != hipSuccess) rc = from_hip(e);
+  fstat_out out{};
+  out.mode = FSTAT_OUT_MAP;
+  out.k_lo = 0;
+  out.k_hi = kh;
+  out.F = scratch;
+  for (size_t ci = 0; rc == FSTAT_OK && ci < cands.size(); ++ci) {
+    apply_split(sp, prec, cands[ci]);
+    if ((e = make_split_tables(sp, prec, st)) != hipSuccess) {
+      rc = from_hip(e);
+      break;
+    }
+    for (int b : batches) {
+      sp.node_cap = b;
+      double ms_min = 1e300;
+      for (int rep = 0; rep < 3 && rc == FSTAT_OK; ++rep) {
+        if ((e = hipEventRecord(ea, st)) != hipSuccess) rc = from_hip(e);
+        if (rc == FSTAT_OK) rc = run_grid(p, nodes.data(), (int64_t)nodes.size(), &out, st);
+        if (rc == FSTAT_OK && (e = hipEventRecord(eb, st)) != hipSuccess) rc = from_hip(e);
+        if (rc == FSTAT_OK && (e = hipEventSynchronize(eb)) != hipSuccess) rc = from_hip(e);
+        float ms = 0.f;
+        if (rc == FSTAT_OK && (e = hipEventElapsedTime(&ms, ea, eb)) != hipSuccess) rc = from_hip(e);
+        if (rc == FSTAT_OK && rep > 0) ms_min = std::min(ms_min, (double)ms);  // rep 0 warms up
+      }
+      if (rc == FSTAT_OK && ms_min < best_ms) {
+        best_ms = ms_min;
+        best_C = cands[ci];
+        best_b = b;
+      }
+    }
+  }
+  (void)hipDeviceSynchronize();
+  if (scratch) (void)hipFree(scratch);
+  if (ea) (void)hipEventDestroy(ea);
+  if (eb) (void)hipEventDestroy(eb);
+  if (st) (void)hipStreamDestroy(st);
+  apply_split(sp, prec, best_C);
+  sp.node_cap = best_b;
+  if (rc != FSTAT_OK) return rc;
+  HIP_TRY(make_split_tables(sp, prec, nullptr));
+  HIP_TRY(hipDeviceSynchronize());
+  cache_store(key, best_C, best_b);
   return FSTAT_OK;
+}
+
+// ===========================================================================
+extern "C" {
+
+const char* fstat_strerror(fstat_status s) {
+  switch (s) {
+    case FSTAT_OK: return "ok";
+    case FSTAT_EINVAL: return "invalid argument";
+    case FSTAT_ENOTINTDAYS: return "observation time is not a whole number of sidereal days";
+    case FSTAT_ENOMEM: return "out of memory";
+    case FSTAT_EDEVICE: return "HIP device error";
+    case FSTAT_EUNSUPPORTED: return "unsupported size";
+    default: return "unknown status";
+  }
+}
+
+fstat_status fstat_plan(const fstat_segment* segs, int32_t nseg, const fstat_detector* det,
+                        const fstat_ephemeris* eph, const fstat_options* opt, fstat_plan_t* out) {
+  if (!segs || nseg <= 0 || !det || !eph || !opt || !out) return FSTAT_EINVAL;
+  if (opt->interp < 0 || opt->interp > 2 || opt->prec < 0 || opt->prec > 1 || opt->max_batch < 0 ||
+      opt->max_batch > 256 || opt->autotune < 0 || opt->autotune > 1)
+    return FSTAT_EINVAL;
+  if (!(eph->sidereal_day_s > 0.0) || !std::isfinite(eph->orbit_radius_m) || !std::isfinite(eph->orbit_omega) ||
+      !std::isfinite(det->radius_m) || !std::isfinite(det->lat_rad))
+    return FSTAT_EINVAL;
+  for (int i = 0; i < nseg; ++i) {
+    fstat_status v = validate_segment(segs[i], *eph, opt->prec);
+    if (v != FSTAT_OK) return v;
+  }
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return FSTAT_EDEVICE;
+  if (opt->device < 0 || opt->device >= ndev) return FSTAT_EINVAL;
+  DeviceGuard guard(opt->device);
+  if (!guard.ok) return FSTAT_EDEVICE;
+
+  fstat_plan_s* p = new (std::nothrow) fstat_plan_s();
+  if (!p) return FSTAT_ENOMEM;
+  p->device = opt->device;
+  p->interp = opt->interp;
+  p->prec = opt->prec;
+  p->max_batch = opt->max_batch;
+  p->segs.resize(nseg);
+  for (int i = 0; i < nseg; ++i) {
+    fstat_status rc = build_segment(segs[i], *det, *eph, opt->prec, opt->interp, p->segs[i]);
+    if (rc != FSTAT_OK) {
+      destroy_plan(p);
+      return rc;
+    }
+  }
+  for (auto& sp : p->segs) sp.node_cap = opt->max_batch > 0 ? opt->max_batch : (opt->prec == 0 ? 16 : 4);
+  hipError_t e = hipEventCreateWithFlags(&p->staged, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking);
+  for (hipEvent_t* ev : {&p->ev_p1[0], &p->ev_p1[1], &p->ev_p2[0], &p->ev_p2[1], &p->ev_sky[0], &p->ev_sky[1], &p->ev_join})
+    if (e == hipSuccess) e = hipEventCreateWithFlags(ev, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    destroy_plan(p);
+    return from_hip(e);
+  }
+  if (opt->autotune) {
+    for (int i = 0; i < nseg; ++i) {
+      fstat_status rc = tune_segment(p, i);
+      if (rc != FSTAT_OK) {
+        destroy_plan(p);
+        return rc;
+      }
+    }
+  }
+  std::vector<SegDev> hs(nseg);
+  for (int i = 0; i < nseg; ++i) hs[i] = p->segs[i].dev;
+  e = hipMalloc(&p->d_segs, nseg * sizeof(SegDev));
+  if (e == hipSuccess) e = hipMemcpy(p->d_segs, hs.data(), nseg * sizeof(SegDev), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    destroy_plan(p);
+    return from_hip(e);
+  }
+  *out = p;
+  return FSTAT_OK;
+}
+
+fstat_status fstat_plan_schedule(fstat_plan_t p, int32_t seg, int32_t* R, int32_t* C, int32_t* B2, int32_t* batch) {
+  if (!p || seg < 0 || seg >= (int32_t)p->segs.size()) return FSTAT_EINVAL;
+  const SegPlan& sp = p->segs[seg];
+  if (R) *R = sp.dev.R;
+  if (C) *C = sp.dev.C;
+  if (B2) *B2 = sp.B2;
+  if (batch) *batch = sp.node_cap;
+  return FSTAT_OK;
+}
+
+void fstat_destroy(fstat_plan_t p) { destroy_plan(p); }
+
+fstat_status fstat_plan_info(fstat_plan_t p, int32_t seg, int64_t* n, int64_t* nfft, double* sigma2, int32_t* R,
+                             int32_t* C) {
+  if (!p || seg < 0 || seg >= (int32_t)p->segs.size()) return FSTAT_EINVAL;
+  const SegDev& d = p->segs[seg].dev;
+  if (n) *n = d.n;
+  if (nfft) *nfft = d.nfft;
+  if (sigma2) *sigma2 = d.sigma2;
+  if (R) *R = d.R;
+  if (C) *C = d.C;
+  return FSTAT_OK;
+}
+
+fstat_status fstat_grid(fstat_plan_t p, const fstat_node* nodes, int64_t n_nodes, const fstat_out* out,
+                        void* hip_stream) {
+  if (!p || !nodes || n_nodes <= 0 || !out) return FSTAT_EINVAL;
+  if (n_nodes > (int64_t)INT32_MAX) return FSTAT_EUNSUPPORTED;
+  if (out->mode < 0 || out->mode > 2) return FSTAT_EINVAL;
+  if (out->k_lo < 0 || out->k_hi <= out->k_lo) return FSTAT_EINVAL;
+  if (out->mode == 0 && !out->F) return FSTAT_EINVAL;
+  if (out->mode == 1 && (!out->Fmax || !out->kmax)) return FSTAT_EINVAL;
+  if (out->mode == 2 && (!out->n_crossings || (out->max_crossings > 0 && !out->crossings) || out->max_crossings < 0))
+    return FSTAT_EINVAL;
+  const int nseg = (int)p->segs.size();
+  for (int64_t i = 0; i < n_nodes; ++i) {
+    const fstat_node& nd = nodes[i];
+    if (nd.seg < 0 || nd.seg >= nseg || !std::isfinite(nd.alpha) || !std::isfinite(nd.delta) ||
+        !std::isfinite(nd.fdot))
+      return FSTAT_EINVAL;
+    if (out->k_hi > p->segs[nd.seg].dev.nfft / 2) return FSTAT_EINVAL;
+  }
+  DeviceGuard guard(p->device);
+  if (!guard.ok) return FSTAT_EDEVICE;
+  return run_grid(p, nodes, n_nodes, out, (hipStream_t)hip_stream);
 }
 
 fstat_status fstat_profile(fstat_plan_t p, int32_t enable) {

@@ -13,8 +13,12 @@
 #pragma once
 #include "internal.h"
 
+// FP32 path: the hardware sine/cosine take their argument in turns
+// (sin(2 pi x)); x is already reduced to [-1/2, 1/2].
 __device__ __forceinline__ void sincos_turns(double x, float& s, float& c) {
-  sincospif(2.0f * (float)x, &s, &c);
+  const float xf = (float)x;
+  s = __builtin_amdgcn_sinf(xf);
+  c = __builtin_amdgcn_cosf(xf);
 }
 __device__ __forceinline__ void sincos_turns(double x, double& s, double& c) {
   sincospi(2.0 * x, &s, &c);

@@ -62,7 +62,7 @@ class _Segment(ctypes.Structure):
 
 class _Options(ctypes.Structure):
     _fields_ = [("interp", ctypes.c_int32), ("prec", ctypes.c_int32), ("device", ctypes.c_int32),
-                ("max_batch", ctypes.c_int32)]
+                ("max_batch", ctypes.c_int32), ("autotune", ctypes.c_int32)]
 
 
 class _Out(ctypes.Structure):
@@ -76,7 +76,8 @@ NODE_DTYPE = np.dtype([("alpha", "<f8"), ("delta", "<f8"), ("fdot", "<f8"), ("se
 CROSSING_DTYPE = np.dtype([("node", "<i8"), ("k", "<i8"), ("F", "<f8")])
 
 EXPORTS = ("fstat_plan", "fstat_grid", "fstat_eval", "fstat_adjoint", "fstat_grad", "fstat_plan_info",
-           "fstat_demod_series", "fstat_profile", "fstat_profile_read", "fstat_destroy", "fstat_strerror")
+           "fstat_demod_series", "fstat_profile", "fstat_profile_read", "fstat_plan_schedule", "fstat_destroy",
+           "fstat_strerror")
 K_SKY, K_PASS1, K_PASS2, K_OTHER = 0, 1, 2, 3
 
 _lib = None
@@ -98,13 +99,14 @@ def lib():
         L.fstat_plan_info.argtypes = [vp, i32, P(i64), P(i64), P(ctypes.c_double), P(i32), P(i32)]
         L.fstat_demod_series.argtypes = [vp, vp, vp, vp]
         L.fstat_profile.argtypes = [vp, i32]
+        L.fstat_plan_schedule.argtypes = [vp, i32, P(i32), P(i32), P(i32), P(i32)]
         L.fstat_profile_read.argtypes = [vp, i32, P(i64), P(ctypes.c_double), P(ctypes.c_double)]
         L.fstat_destroy.argtypes = [vp]
         L.fstat_strerror.argtypes = [i32]
         L.fstat_strerror.restype = ctypes.c_char_p
         L.fstat_destroy.restype = None
         for name in ("fstat_plan", "fstat_grid", "fstat_eval", "fstat_adjoint", "fstat_grad", "fstat_plan_info",
-                     "fstat_demod_series", "fstat_profile", "fstat_profile_read"):
+                     "fstat_demod_series", "fstat_profile", "fstat_profile_read", "fstat_plan_schedule"):
             getattr(L, name).restype = i32
         _lib = L
     return _lib
@@ -188,7 +190,8 @@ class Plan:
     """A plan of fstat_plan: segments on the device, prepared for grid calls."""
 
     def __init__(self, segments: Sequence[SegmentSpec], det: Detector, eph: Ephemeris,
-                 interp: int = LINEAR_UP2, prec: int = FP32, device: int = 0, max_batch: int = 0):
+                 interp: int = LINEAR_UP2, prec: int = FP32, device: int = 0, max_batch: int = 0,
+                 autotune: bool = False):
         L = lib()
         self._keep = []
         segs = (_Segment * len(segments))()
@@ -210,7 +213,7 @@ class Plan:
         d = _Detector(det.lat, det.lon, det.gamma, det.zeta, det.radius)
         e = _Ephemeris(eph.obliquity, eph.orbit_radius, eph.orbit_omega, eph.orbit_phase0, eph.sidereal_day,
                        eph.gmst0)
-        o = _Options(interp, prec, device, max_batch)
+        o = _Options(interp, prec, device, max_batch, 1 if autotune else 0)
         h = ctypes.c_void_p()
         _check(L.fstat_plan(segs, len(segments), ctypes.byref(d), ctypes.byref(e), ctypes.byref(o),
                             ctypes.byref(h)), "fstat_plan")
@@ -239,6 +242,13 @@ class Plan:
         _check(lib().fstat_plan_info(self._h, seg, ctypes.byref(n), ctypes.byref(nfft), ctypes.byref(s2),
                                      ctypes.byref(R), ctypes.byref(C)), "fstat_plan_info")
         return dict(n=n.value, nfft=nfft.value, sigma2=s2.value, R=R.value, C=C.value)
+
+    def schedule(self, seg: int = 0) -> dict:
+        """The FFT split and batch size in use for a segment."""
+        R, C, B2, b = (ctypes.c_int32() for _ in range(4))
+        _check(lib().fstat_plan_schedule(self._h, seg, ctypes.byref(R), ctypes.byref(C), ctypes.byref(B2),
+                                         ctypes.byref(b)), "fstat_plan_schedule")
+        return dict(R=R.value, C=C.value, B2=B2.value, batch=b.value)
 
     def profile(self, enable: bool = True):
         """Enable (and reset) or disable per-launch kernel timing."""

@@ -46,7 +46,7 @@ def _plan_status(n=43082, dt=2.0, days=1, nfft=0, interp=1, prec=0, x=None, det=
     dd = fstat._Detector(d.lat, d.lon, d.gamma, d.zeta, d.radius)
     e = fstat.Ephemeris()
     ee = fstat._Ephemeris(e.obliquity, e.orbit_radius, e.orbit_omega, e.orbit_phase0, e.sidereal_day, e.gmst0)
-    o = fstat._Options(interp, prec, 0, 0)
+    o = fstat._Options(interp, prec, 0, 0, 0)
     h = ctypes.c_void_p()
     return L.fstat_plan(ctypes.byref(seg), 1, ctypes.byref(dd), ctypes.byref(ee), ctypes.byref(o), ctypes.byref(h))
 

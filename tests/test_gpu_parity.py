@@ -225,3 +225,52 @@ def test_repeated_calls_are_bitwise_identical():
     a = plan.grid_map(nodes, 0, seg.fft_len // 2).clone()
     b = plan.grid_map(nodes, 0, seg.fft_len // 2)
     assert torch.equal(a, b)
+
+
+def test_autotuned_plan_and_cache(tmp_path, monkeypatch):
+    # the tuner picks a valid split for nfft = 2^16 and the results still match
+    # the oracle; a second plan reads the same choice back from the cache file
+    w = synth.TINY
+    g, x, sigs = synth.segment_data(w)
+    p = sigs[0]
+    x = x + model.injection(w.n, w.dt, 0.0, p, synth.F_REF, 1.0, DET, EPH)
+    seg = method.Segment(x=x, dt=w.dt, n_days=w.days, f_ref=synth.F_REF, sigma2=1.0, nfft=w.nfft)
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("FSTAT_TUNE_CACHE", str(cache))
+    banner("autotune")
+    specs = [fstat.SegmentSpec(x=seg.x, dt=seg.dt, n_days=seg.n_days, f_ref=seg.f_ref, sigma2=1.0, nfft=w.nfft)]
+    plan = fstat.Plan(specs, fstat.detector_spec(DET), fstat.ephemeris_spec(EPH), interp=w.interp,
+                      prec=fstat.FP32, autotune=True)
+    sch = plan.schedule()
+    assert sch["C"] in (1024, 2048, 4096) and sch["R"] * sch["C"] == w.nfft and sch["batch"] in (8, 16, 32)
+    assert cache.read_text().startswith("fstat-tune-v1")
+    nodes = fstat.nodes_array(np.full(3, p["alpha"]), np.full(3, p["delta"]), [p["fdot"], 0.0, -5e-10])
+    F = plan.grid_map(nodes, 0, w.nfft // 2).cpu().numpy()
+    for i, nd in enumerate(nodes):
+        ref = oracle_map(seg, nd["fdot"], nd["alpha"], nd["delta"], w.interp, np.arange(w.nfft // 2))
+        assert f_error(F[i], ref) < PREC_TOL[fstat.FP32]
+    plan2 = fstat.Plan(specs, fstat.detector_spec(DET), fstat.ephemeris_spec(EPH), interp=w.interp,
+                       prec=fstat.FP32, autotune=True)
+    assert plan2.schedule() == sch
+    assert len(cache.read_text().splitlines()) == 1
+
+
+@pytest.mark.parametrize("C", [1024, 2048, 4096])
+def test_every_split_gives_the_same_map(C, tmp_path, monkeypatch):
+    # force each split through the cache file: same bins, FP32 rounding apart
+    w = synth.TINY
+    g, x, sigs = synth.segment_data(w)
+    cache = tmp_path / "tune.txt"
+    cache.write_text("fstat-tune-v1 0 %d %d %d %d 8\n" % (w.interp, w.nfft, w.n, C))
+    monkeypatch.setenv("FSTAT_TUNE_CACHE", str(cache))
+    banner("split", C)
+    specs = [fstat.SegmentSpec(x=x, dt=w.dt, n_days=w.days, f_ref=synth.F_REF, sigma2=1.0, nfft=w.nfft)]
+    plan = fstat.Plan(specs, fstat.detector_spec(DET), fstat.ephemeris_spec(EPH), interp=w.interp,
+                      prec=fstat.FP32, autotune=True)
+    assert plan.schedule()["C"] == C and plan.schedule()["batch"] == 8
+    nodes = fstat.nodes_array([0.3, 2.0], [0.1, -0.7], [0.0, -5e-10])
+    F = plan.grid_map(nodes, 0, w.nfft // 2).cpu().numpy()
+    seg = method.Segment(x=x, dt=w.dt, n_days=w.days, f_ref=synth.F_REF, sigma2=1.0, nfft=w.nfft)
+    for i, nd in enumerate(nodes):
+        ref = oracle_map(seg, nd["fdot"], nd["alpha"], nd["delta"], w.interp, np.arange(w.nfft // 2))
+        assert f_error(F[i], ref) < PREC_TOL[fstat.FP32]

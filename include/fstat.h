@@ -116,6 +116,9 @@ typedef struct {
                         environment variable FSTAT_TUNE_CACHE if it is set.
                         0: fixed defaults. */
 } fstat_options;
+/* Environment: FSTAT_STREAMS=1 at plan creation runs the whole grid pipeline
+ * on the caller's stream (no overlap of the two FFT passes of consecutive node
+ * batches); meant for per-kernel timing. */
 
 typedef struct fstat_plan_s *fstat_plan_t;
 

@@ -67,6 +67,7 @@ struct fstat_plan_s {
   hipEvent_t staged = nullptr;
   bool staged_pending = false;
   hipStream_t side = nullptr;  // second stream of the grid pipeline (default priority)
+  bool one_stream = false;
   hipEvent_t ev_p1[2] = {nullptr, nullptr}, ev_p2[2] = {nullptr, nullptr}, ev_sky[2] = {nullptr, nullptr};
   hipEvent_t ev_join = nullptr;
 };
@@ -475,7 +476,7 @@ fstat_status run_grid(fstat_plan_s* p, const fstat_node* nodes, int64_t n_nodes,
   // caller's stream, the second pass on the plan's side stream, so that pass 1
   // of chunk c+1 (arithmetic-bound) overlaps pass 2 of chunk c (memory-bound).
   // Chunk c uses spill buffer c % 2; sky batch s uses sky set s % 2.
-  hipStream_t s2 = p->side;
+  hipStream_t s2 = p->one_stream ? st : p->side;
   const double er = (double)elem_real(prec);
   int64_t chunk = 0;
   int sbi = 0;
@@ -506,7 +507,7 @@ fstat_status run_grid(fstat_plan_s* p, const fstat_node* nodes, int64_t n_nodes,
       HIP_TRY(hipEventRecord(p->ev_p1[chunk % 2], st));
       HIP_TRY(hipStreamWaitEvent(s2, p->ev_p1[chunk % 2], 0));
       HIP_TRY(timed(p, FSTAT_K_PASS2, sbytes + outb, s2, [&] {
-        return fsk::grid_pass2(prec, d.R, sp.B2, d, spill, dn, nn, ss.coef, sp.twR, go, d_part, s2);
+        return fsk::grid_pass2(prec, d.R, d, spill, dn, nn, ss.coef, sp.twR, go, d_part, s2);
       }));
       if (out->mode == 1)
         HIP_TRY(timed(p, FSTAT_K_OTHER, 0.0, s2,
@@ -700,6 +701,7 @@ fstat_status fstat_plan(const fstat_segment* segs, int32_t nseg, const fstat_det
     }
   }
   for (auto& sp : p->segs) sp.node_cap = opt->max_batch > 0 ? opt->max_batch : (opt->prec == 0 ? 16 : 4);
+  if (const char* s1 = std::getenv("FSTAT_STREAMS")) p->one_stream = s1[0] == '1';
   hipError_t e = hipEventCreateWithFlags(&p->staged, hipEventDisableTiming);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking);
   for (hipEvent_t* ev : {&p->ev_p1[0], &p->ev_p1[1], &p->ev_p2[0], &p->ev_p2[1], &p->ev_sky[0], &p->ev_sky[1], &p->ev_join})

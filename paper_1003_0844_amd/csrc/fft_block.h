@@ -5,10 +5,7 @@
 // reads its inputs through a Load functor (global memory, or values computed
 // on the fly), the last stage hands each butterfly's Rs outputs to the Store
 // functor as store(i, col, v, integral_constant STRIDE): v[q] is output
-// i + q STRIDE;
-// the stages
-// in between exchange through LDS, in place, one barrier before and one after
-// each write phase.
+// i + q STRIDE.  Consecutive stages exchange their data through LDS.
 //
 // Stockham stage with span Ns and radix Rs (butterfly i, k = i mod Ns):
 //   inputs  x[i + q L/Rs]            q < Rs
@@ -22,6 +19,11 @@
 // one pad slot per 16 elements breaks the power-of-two strides of the write
 // phase.  Threads map column-fastest (col = b mod NCOL) so that global loads
 // and stores of NCOL adjacent columns are contiguous.
+//
+// Pair elements (the a- and b-weighted series of one node) cross the LDS in
+// two rounds, a halves first, then b halves, through a buffer of single
+// complex values: the workgroup needs half the LDS, so twice as many
+// workgroups fit on a CU, at the price of two more barriers per exchange.
 #pragma once
 #include <type_traits>
 
@@ -48,6 +50,15 @@ constexpr int fft_span(int L, int s) {
   for (int i = 0; i < s; ++i) p *= fft_radix(L, i);
   return p;
 }
+
+template <int L, int NCOL, int BLOCK, int S>
+struct StageShape {
+  static constexpr int Rs = fft_radix(L, S);
+  static constexpr int Ns = fft_span(L, S);
+  static constexpr int NB = NCOL * (L / Rs);       // butterflies of the stage
+  static constexpr int PER = (NB + BLOCK - 1) / BLOCK;  // butterflies per thread
+};
+
 // p[q] = w^q, q < R: squares for even q, one more factor w for odd q
 // (at most six products deep for R = 16)
 template <int R, typename T>
@@ -58,6 +69,14 @@ __device__ __forceinline__ void powers(cpx<T> w, cpx<T> (&p)[R]) {
   for (int q = 2; q < R; ++q) p[q] = (q % 2 == 0) ? cmul(p[q / 2], p[q / 2]) : cmul(p[q - 1], w);
 }
 
+// Thread index as an opaque value: index arithmetic derived from it is redone
+// per transform instead of being kept live across a loop of transforms.
+__device__ __forceinline__ int fft_tid() {
+  int t = threadIdx.x;
+  asm volatile("" : "+v"(t));
+  return t;
+}
+
 constexpr int lds_slots(int L, int NCOL) { return L * NCOL + ((L * NCOL) >> 4); }
 
 __device__ __forceinline__ int lds_addr(int idx, int col, int ncol) {
@@ -65,36 +84,121 @@ __device__ __forceinline__ int lds_addr(int idx, int col, int ncol) {
   return lin + (lin >> 4);
 }
 
-template <typename E, int L, int NCOL, int BLOCK, int DIR, int S, class Load, class Store>
-__device__ __forceinline__ void fft_stage(E* __restrict__ lds,
-                                          const cpx<typename elem_traits<E>::real>* __restrict__ tw,
-                                          Load& load, Store& store) {
-  using T = typename elem_traits<E>::real;
-  constexpr int NS = fft_nstages(L);
-  constexpr int Rs = fft_radix(L, S);
-  constexpr int Ns = fft_span(L, S);
-  constexpr int NB = NCOL * (L / Rs);
-  constexpr int PER = (NB + BLOCK - 1) / BLOCK;
-  constexpr int TWS = L / (Ns * Rs);  // table stride: table holds exp(-2 pi i m / L)
-  const int tid = threadIdx.x;
+// LDS slot type of an element type: pairs are exchanged half by half.
+template <typename E>
+struct lds_of {
+  using type = E;
+  static constexpr int rounds = 1;
+};
+template <typename T>
+struct lds_of<Pair<T>> {
+  using type = cpx<T>;
+  static constexpr int rounds = 2;
+};
+template <typename E>
+using lds_t = typename lds_of<E>::type;
 
-  E v[PER][Rs];
+template <int H, typename T>
+__device__ __forceinline__ cpx<T>& part(Pair<T>& e) {
+  if constexpr (H == 0) return e.a;
+  else return e.b;
+}
+template <int H, typename T>
+__device__ __forceinline__ cpx<T>& part(cpx<T>& e) {
+  return e;
+}
+
+// Outputs of stage S (registers v) become the inputs of stage S+1 (registers
+// u) through LDS.  The leading barrier protects the previous exchange's reads.
+template <typename E, int L, int NCOL, int BLOCK, int S, int PV, int RV, int PU, int RU>
+__device__ __forceinline__ void exchange(lds_t<E>* __restrict__ lds, E (&v)[PV][RV], E (&u)[PU][RU]) {
+  using G0 = StageShape<L, NCOL, BLOCK, S>;
+  using G1 = StageShape<L, NCOL, BLOCK, S + 1>;
+  const int tid = fft_tid();
+  auto put = [&](auto h) {
+    constexpr int H = decltype(h)::value;
 #pragma unroll
-  for (int m = 0; m < PER; ++m) {
-    const int b = tid + m * BLOCK;
-    if (NB % BLOCK == 0 || b < NB) {
-      const int col = b % NCOL;
-      const int i = b / NCOL;
-      const int k = i % Ns;
+    for (int m = 0; m < PV; ++m) {
+      const int b = tid + m * BLOCK;
+      if (G0::NB % BLOCK == 0 || b < G0::NB) {
+        const int col = b % NCOL;
+        const int i = b / NCOL;
+        const int k = i % G0::Ns;
+        const int base = (i / G0::Ns) * G0::Ns * G0::Rs + k;
 #pragma unroll
-      for (int q = 0; q < Rs; ++q) {
-        const int idx = i + q * (L / Rs);
-        if constexpr (S == 0) v[m][q] = load(idx, col);
-        else v[m][q] = lds[lds_addr(idx, col, NCOL)];
+        for (int q = 0; q < RV; ++q) lds[lds_addr(base + q * G0::Ns, col, NCOL)] = part<H>(v[m][q]);
       }
+    }
+  };
+  auto get = [&](auto h) {
+    constexpr int H = decltype(h)::value;
+#pragma unroll
+    for (int m = 0; m < PU; ++m) {
+      const int b = tid + m * BLOCK;
+      if (G1::NB % BLOCK == 0 || b < G1::NB) {
+        const int col = b % NCOL;
+        const int i = b / NCOL;
+#pragma unroll
+        for (int q = 0; q < RU; ++q) part<H>(u[m][q]) = lds[lds_addr(i + q * (L / G1::Rs), col, NCOL)];
+      }
+    }
+  };
+  if constexpr (S > 0) __syncthreads();
+  put(std::integral_constant<int, 0>());
+  __syncthreads();
+  get(std::integral_constant<int, 0>());
+  if constexpr (lds_of<E>::rounds == 2) {
+    __syncthreads();
+    put(std::integral_constant<int, 1>());
+    __syncthreads();
+    get(std::integral_constant<int, 1>());
+  }
+}
+
+// Issue the stage-0 loads of one transform into v.
+template <typename E, int L, int NCOL, int BLOCK, class Load>
+__device__ __forceinline__ void fft_fetch(Load& load,
+                                          E (&v)[StageShape<L, NCOL, BLOCK, 0>::PER][StageShape<L, NCOL, BLOCK, 0>::Rs]) {
+  using G = StageShape<L, NCOL, BLOCK, 0>;
+  const int tid = fft_tid();
+#pragma unroll
+  for (int m = 0; m < G::PER; ++m) {
+    const int b = tid + m * BLOCK;
+    if (G::NB % BLOCK == 0 || b < G::NB) {
+#pragma unroll
+      for (int q = 0; q < G::Rs; ++q) v[m][q] = load(b / NCOL + q * (L / G::Rs), b % NCOL);
+    }
+  }
+}
+
+// Stage twiddle bases w^k, k = i mod Ns, read from the table
+// exp(-2 pi i m / L) as each butterfly needs them (one load per butterfly).
+template <typename T, int L>
+struct TwTable {
+  const cpx<T>* __restrict__ tab;
+  template <int S>
+  __device__ __forceinline__ cpx<T> operator()(std::integral_constant<int, S>, int, int k) const {
+    return tab[k * (L / (fft_span(L, S) * fft_radix(L, S)))];
+  }
+};
+
+// Stage S on the registers v (the inputs of the stage).
+template <typename E, int L, int NCOL, int BLOCK, int DIR, int S, class TwF, class Store>
+__device__ __forceinline__ void fft_stage(lds_t<E>* __restrict__ lds, const TwF& twf, Store& store,
+                                          E (&v)[StageShape<L, NCOL, BLOCK, S>::PER][StageShape<L, NCOL, BLOCK, S>::Rs]) {
+  using T = typename elem_traits<E>::real;
+  using G = StageShape<L, NCOL, BLOCK, S>;
+  constexpr int NS = fft_nstages(L);
+  constexpr int Rs = G::Rs;
+  const int tid = fft_tid();
+
+#pragma unroll
+  for (int m = 0; m < G::PER; ++m) {
+    const int b = tid + m * BLOCK;
+    if (G::NB % BLOCK == 0 || b < G::NB) {
       if constexpr (S > 0) {
-        // one table load per butterfly, the other powers by multiplication
-        cpx<T> w = tw[k * TWS];
+        // one twiddle base per butterfly, the other powers by multiplication
+        cpx<T> w = twf(std::integral_constant<int, S>(), m, (b / NCOL) % G::Ns);
         if constexpr (DIR > 0) w.y = -w.y;
         cpx<T> pw[Rs];
         powers<Rs>(w, pw);
@@ -107,37 +211,26 @@ __device__ __forceinline__ void fft_stage(E* __restrict__ lds,
 
   if constexpr (S == NS - 1) {
 #pragma unroll
-    for (int m = 0; m < PER; ++m) {
+    for (int m = 0; m < G::PER; ++m) {
       const int b = tid + m * BLOCK;
-      if (NB % BLOCK == 0 || b < NB) {
-        const int col = b % NCOL;
-        const int i = b / NCOL;
-        store(i, col, v[m], std::integral_constant<int, L / Rs>());
-      }
+      if (G::NB % BLOCK == 0 || b < G::NB) store(b / NCOL, b % NCOL, v[m], std::integral_constant<int, L / Rs>());
     }
   } else {
-    if constexpr (S > 0) __syncthreads();
-#pragma unroll
-    for (int m = 0; m < PER; ++m) {
-      const int b = tid + m * BLOCK;
-      if (NB % BLOCK == 0 || b < NB) {
-        const int col = b % NCOL;
-        const int i = b / NCOL;
-        const int k = i % Ns;
-        const int base = (i / Ns) * Ns * Rs + k;
-#pragma unroll
-        for (int q = 0; q < Rs; ++q) lds[lds_addr(base + q * Ns, col, NCOL)] = v[m][q];
-      }
-    }
-    __syncthreads();
-    fft_stage<E, L, NCOL, BLOCK, DIR, S + 1>(lds, tw, load, store);
+    using G1 = StageShape<L, NCOL, BLOCK, S + 1>;
+    E u[G1::PER][G1::Rs];
+    exchange<E, L, NCOL, BLOCK, S>(lds, v, u);
+    fft_stage<E, L, NCOL, BLOCK, DIR, S + 1>(lds, twf, store, u);
   }
 }
 
 // Transform NCOL columns of length L.  tw: exp(-2 pi i m / L), m < L.
+// lds: lds_slots(L, NCOL) slots of lds_t<E>.
 template <typename E, int L, int NCOL, int BLOCK, int DIR, class Load, class Store>
-__device__ __forceinline__ void block_fft(E* __restrict__ lds,
+__device__ __forceinline__ void block_fft(lds_t<E>* __restrict__ lds,
                                           const cpx<typename elem_traits<E>::real>* __restrict__ tw,
                                           Load& load, Store& store) {
-  fft_stage<E, L, NCOL, BLOCK, DIR, 0>(lds, tw, load, store);
+  using G = StageShape<L, NCOL, BLOCK, 0>;
+  E v[G::PER][G::Rs];
+  fft_fetch<E, L, NCOL, BLOCK>(load, v);
+  fft_stage<E, L, NCOL, BLOCK, DIR, 0>(lds, TwTable<typename elem_traits<E>::real, L>{tw}, store, v);
 }

@@ -41,7 +41,7 @@ k_pass1(SegDev sg, const Quad<T>* __restrict__ quads, int64_t qstride, const Sky
         const NodeDev* __restrict__ nodes, const cpx<T>* __restrict__ twC, const cpx<T>* __restrict__ twlo,
         const cpx<T>* __restrict__ twhi, Pair<T>* __restrict__ spill) {
   constexpr int BLOCK = cfg_block(C / 16);
-  __shared__ Pair<T> lds[lds_slots(C, 1)];
+  __shared__ lds_t<Pair<T>> lds[lds_slots(C, 1)];
   const int r = blockIdx.x;
   const int nd = blockIdx.y;
   const NodeDev node = nodes[nd];
@@ -72,6 +72,7 @@ k_pass1(SegDev sg, const Quad<T>* __restrict__ quads, int64_t qstride, const Sky
   block_fft<Pair<T>, C, 1, BLOCK, -1>(lds, twC, load, store);
 }
 
+// Pass 2 for the column block cb (B2 adjacent k2) of node nd.
 template <typename T, int R, int MODE>
 __global__ void __launch_bounds__(cfg_block(cfg_B2<T>(R) * R / 16))
 k_pass2(SegDev sg, const Pair<T>* __restrict__ spill, const NodeDev* __restrict__ nodes,
@@ -79,7 +80,7 @@ k_pass2(SegDev sg, const Pair<T>* __restrict__ spill, const NodeDev* __restrict_
         MaxPartial* __restrict__ part) {
   constexpr int B2 = cfg_B2<T>(R);
   constexpr int BLOCK = cfg_block(B2 * R / 16);
-  __shared__ Pair<T> lds[lds_slots(R, B2)];
+  __shared__ lds_t<Pair<T>> lds[lds_slots(R, B2)];
   const int nd = blockIdx.y;
   const int cb = xcd_local(blockIdx.x, gridDim.x);
   const NodeDev node = nodes[nd];
@@ -225,7 +226,7 @@ hipError_t grid_pass1(int prec, int C, const SegDev& seg, const void* quads, int
   return launch_pass1<double>(C, seg, quads, qstride, sky, nodes, nnodes, twC, twlo, twhi, spill, st);
 }
 
-hipError_t grid_pass2(int prec, int R, int, const SegDev& seg, const void* spill, const NodeDev* nodes, int nnodes,
+hipError_t grid_pass2(int prec, int R, const SegDev& seg, const void* spill, const NodeDev* nodes, int nnodes,
                       const SkyCoef* coef, const void* twR, const GridOut& out, MaxPartial* part, hipStream_t st) {
   if (nnodes <= 0) return hipSuccess;
   if (prec == 0) {

@@ -91,8 +91,8 @@ int pass2_b2(int prec, int R);
 hipError_t grid_pass1(int prec, int C, const SegDev& seg, const void* d_quads, int64_t quad_stride,
                       const SkyConst* d_sky, const NodeDev* d_nodes, int nnodes, const void* tw_C,
                       const void* tw_lo, const void* tw_hi, void* d_spill, hipStream_t st);
-hipError_t grid_pass2(int prec, int R, int B2, const SegDev& seg, const void* d_spill, const NodeDev* d_nodes,
-                      int nnodes, const SkyCoef* d_coef, const void* tw_R, const GridOut& out, MaxPartial* d_part,
+hipError_t grid_pass2(int prec, int R, const SegDev& seg, const void* d_spill, const NodeDev* d_nodes, int nnodes,
+                      const SkyCoef* d_coef, const void* tw_R, const GridOut& out, MaxPartial* d_part,
                       hipStream_t st);
 hipError_t max_finalize(const MaxPartial* d_part, int nparts, const NodeDev* d_nodes, int nnodes, int prec,
                         const GridOut& out, hipStream_t st);

@@ -172,6 +172,23 @@ typedef struct {
 fstat_status fstat_grid(fstat_plan_t p, const fstat_node *nodes, int64_t n_nodes, const fstat_out *out,
                         void *hip_stream);
 
+/* The batched grid of Sec. VI as one replayable launch: records the whole
+ * launch sequence of fstat_grid(p, nodes, n_nodes, out) -- every segment and
+ * sky batch of the node list, both FFT passes -- into a HIP graph with a device
+ * workspace of its own.  Arguments and errors as for fstat_grid; synchronous.
+ * The node list is copied; the output buffers named in *out are the ones every
+ * launch writes.  The graph reads the plan's segment data, so destroy it before
+ * the plan.  *g receives the graph. */
+typedef struct fstat_graph_s *fstat_graph_t;
+fstat_status fstat_graph_create(fstat_plan_t p, const fstat_node *nodes, int64_t n_nodes, const fstat_out *out,
+                                fstat_graph_t *g);
+/* Enqueue one replay on hip_stream: the outputs are rewritten exactly as a
+ * fstat_grid call with the recorded arguments would write them.  Replays of one
+ * graph that overlap in time (on different streams) race on its workspace. */
+fstat_status fstat_graph_launch(fstat_graph_t g, void *hip_stream);
+/* Waits for the device, then frees the graph and its workspace. */
+void fstat_graph_destroy(fstat_graph_t g);
+
 /* F at continuous parameters by the same resampling method (the sum over the
  * barycentric grid with e^{-2 pi i f j dt} in place of the FFT kernel), for
  * candidate refinement off the grid.  All FP64.

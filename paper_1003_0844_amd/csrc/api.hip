@@ -70,6 +70,15 @@ struct fstat_plan_s {
   bool one_stream = false;
   hipEvent_t ev_p1[2] = {nullptr, nullptr}, ev_p2[2] = {nullptr, nullptr}, ev_sky[2] = {nullptr, nullptr};
   hipEvent_t ev_join = nullptr;
+  bool capturing = false;  // a graph capture is recording the launch sequence
+};
+
+// A grid call recorded once as a HIP graph, with a workspace of its own.
+struct fstat_graph_s {
+  fstat_plan_s* plan = nullptr;
+  void* ws = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
 };
 
 namespace {
@@ -322,7 +331,7 @@ size_t align_up(size_t v, size_t a = 256) { return (v + a - 1) / a * a; }
 // Launch through f(); when profiling is on, bracket it with two events.
 template <class F>
 hipError_t timed(fstat_plan_s* p, int kind, double bytes, hipStream_t st, F&& f) {
-  if (!p->prof.on) return f();
+  if (!p->prof.on || p->capturing) return f();
   ProfPair pr{};
   if (!p->prof.pool.empty()) {
     pr = p->prof.pool.back();
@@ -365,12 +374,20 @@ struct SkyBatch {
 
 }  // namespace
 
-// The launch sequence of a grid call (arguments already validated).
-fstat_status run_grid(fstat_plan_s* p, const fstat_node* nodes, int64_t n_nodes, const fstat_out* out,
-                      hipStream_t st) {
-  const int prec = p->prec;
+// Host-side schedule of a grid call: nodes grouped by segment and sky position
+// into batches, and the workspace layout they need.
+struct GridSched {
+  std::vector<double> sky_ad;   // (alpha, delta) per sky of the call
+  std::vector<NodeDev> ndev;    // per node, grouped by batch
+  std::vector<SkyBatch> batches;
+  size_t max_quads = 0, max_spill = 0, max_part = 0, max_abc = 0;
+  int max_sky = 0;
+  size_t desc_bytes = 0;        // sky list + node list, staged at the start of the workspace
+  size_t need_ws = 0;
+};
 
-  // ---- group nodes: by segment, then by sky position ----
+void schedule_grid(const fstat_plan_s* p, const fstat_node* nodes, int64_t n_nodes, GridSched& gs) {
+  const int prec = p->prec;
   std::vector<int64_t> order(n_nodes);
   for (int64_t i = 0; i < n_nodes; ++i) order[i] = i;
   std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
@@ -379,62 +396,68 @@ fstat_status run_grid(fstat_plan_s* p, const fstat_node* nodes, int64_t n_nodes,
     if (x.alpha != y.alpha) return x.alpha < y.alpha;
     return x.delta < y.delta;
   });
-  std::vector<double> sky_ad;      // (alpha, delta) per sky of the call
-  std::vector<NodeDev> ndev;       // per node, grouped by batch
-  std::vector<SkyBatch> batches;
-  // batch sizing per segment
-  size_t need_ws = 0;
-  {
-    int64_t i = 0;
-    while (i < n_nodes) {
-      const int sg = nodes[order[i]].seg;
-      const SegDev& d = p->segs[sg].dev;
-      const size_t quad_bytes = (size_t)d.R * d.Ceff * 4 * elem_real(prec);
-      int sky_cap = (int)std::max<size_t>(1, std::min<size_t>(64, ((size_t)1 << 30) / quad_bytes));
-      SkyBatch b{sg, (int)(sky_ad.size() / 2), 0, (int)ndev.size(), 0};
-      while (i < n_nodes && nodes[order[i]].seg == sg) {
-        const fstat_node& nd = nodes[order[i]];
-        const bool new_sky = b.nsky == 0 || sky_ad[sky_ad.size() - 2] != nd.alpha || sky_ad.back() != nd.delta;
-        if (new_sky) {
-          if (b.nsky == sky_cap) {
-            batches.push_back(b);
-            b = SkyBatch{sg, (int)(sky_ad.size() / 2), 0, (int)ndev.size(), 0};
-          }
-          sky_ad.push_back(nd.alpha);
-          sky_ad.push_back(nd.delta);
-          ++b.nsky;
+  std::vector<double>& sky_ad = gs.sky_ad;
+  std::vector<NodeDev>& ndev = gs.ndev;
+  std::vector<SkyBatch>& batches = gs.batches;
+  int64_t i = 0;
+  while (i < n_nodes) {
+    const int sg = nodes[order[i]].seg;
+    const SegDev& d = p->segs[sg].dev;
+    const size_t quad_bytes = (size_t)d.R * d.Ceff * 4 * elem_real(prec);
+    int sky_cap = (int)std::max<size_t>(1, std::min<size_t>(64, ((size_t)1 << 30) / quad_bytes));
+    SkyBatch b{sg, (int)(sky_ad.size() / 2), 0, (int)ndev.size(), 0};
+    while (i < n_nodes && nodes[order[i]].seg == sg) {
+      const fstat_node& nd = nodes[order[i]];
+      const bool new_sky = b.nsky == 0 || sky_ad[sky_ad.size() - 2] != nd.alpha || sky_ad.back() != nd.delta;
+      if (new_sky) {
+        if (b.nsky == sky_cap) {
+          batches.push_back(b);
+          b = SkyBatch{sg, (int)(sky_ad.size() / 2), 0, (int)ndev.size(), 0};
         }
-        ndev.push_back(NodeDev{nd.fdot, b.nsky - 1, (int32_t)order[i]});
-        ++b.nnode;
-        ++i;
+        sky_ad.push_back(nd.alpha);
+        sky_ad.push_back(nd.delta);
+        ++b.nsky;
       }
-      batches.push_back(b);
+      ndev.push_back(NodeDev{nd.fdot, b.nsky - 1, (int32_t)order[i]});
+      ++b.nnode;
+      ++i;
     }
+    batches.push_back(b);
   }
   // workspace: descriptors; two sets of sky data (one per sky-batch parity);
   // two spill buffers (one per node-chunk parity); max partials
-  size_t max_quads = 0, max_spill = 0, max_part = 0, max_abc = 0;
-  int max_sky = 0;
-  for (const auto& b : batches) {
-    const SegPlan& sp = p->segs[b.seg];
+  for (const auto& bt : batches) {
+    const SegPlan& sp = p->segs[bt.seg];
     const SegDev& d = sp.dev;
-    max_quads = std::max(max_quads, (size_t)b.nsky * d.R * d.Ceff * 4 * elem_real(prec));
-    max_spill = std::max(max_spill, (size_t)sp.node_cap * d.nfft * 4 * elem_real(prec));
-    max_part = std::max(max_part, (size_t)sp.node_cap * (d.C / sp.B2) * sizeof(MaxPartial));
-    max_abc = std::max(max_abc, (size_t)b.nsky * fsk::sky_prep_blocks(d) * 3 * sizeof(double));
-    max_sky = std::max(max_sky, b.nsky);
+    gs.max_quads = std::max(gs.max_quads, (size_t)bt.nsky * d.R * d.Ceff * 4 * elem_real(prec));
+    gs.max_spill = std::max(gs.max_spill, (size_t)sp.node_cap * d.nfft * 4 * elem_real(prec));
+    gs.max_part = std::max(gs.max_part, (size_t)sp.node_cap * (d.C / sp.B2) * sizeof(MaxPartial));
+    gs.max_abc = std::max(gs.max_abc, (size_t)bt.nsky * fsk::sky_prep_blocks(d) * 3 * sizeof(double));
+    gs.max_sky = std::max(gs.max_sky, bt.nsky);
   }
-  const size_t desc_bytes = align_up(sky_ad.size() * sizeof(double)) + align_up(ndev.size() * sizeof(NodeDev));
-  const size_t set_bytes = align_up(max_quads) + align_up(max_abc + 8) + align_up(max_sky * sizeof(SkyConst)) +
-                           align_up(max_sky * sizeof(SkyCoef));
-  need_ws = desc_bytes + 2 * set_bytes + 2 * align_up(max_spill) + align_up(max_part + 16) + 4096;
-  fstat_status rc = ensure_ws(p, need_ws);
-  if (rc != FSTAT_OK) return rc;
-  rc = ensure_pinned(p, desc_bytes);
-  if (rc != FSTAT_OK) return rc;
-  Carve cv{(char*)p->ws};
-  double* d_ad = cv.take<double>(sky_ad.size());
-  NodeDev* d_nodes = cv.take<NodeDev>(ndev.size());
+  gs.desc_bytes = align_up(sky_ad.size() * sizeof(double)) + align_up(ndev.size() * sizeof(NodeDev));
+  const size_t set_bytes = align_up(gs.max_quads) + align_up(gs.max_abc + 8) + align_up(gs.max_sky * sizeof(SkyConst)) +
+                           align_up(gs.max_sky * sizeof(SkyCoef));
+  gs.need_ws = gs.desc_bytes + 2 * set_bytes + 2 * align_up(gs.max_spill) + align_up(gs.max_part + 16) + 4096;
+}
+
+// Copy the call's descriptors (sky list, node list) into host memory laid out
+// as the start of the workspace.
+void pack_descriptors(const GridSched& gs, char* hp) {
+  std::memcpy(hp, gs.sky_ad.data(), gs.sky_ad.size() * sizeof(double));
+  std::memcpy(hp + align_up(gs.sky_ad.size() * sizeof(double)), gs.ndev.data(), gs.ndev.size() * sizeof(NodeDev));
+}
+
+// The launch sequence of a grid call on stream st; ws holds gs.need_ws bytes
+// whose first gs.desc_bytes are the staged descriptors.
+fstat_status launch_grid(fstat_plan_s* p, const GridSched& gs, void* ws, const fstat_out* out, hipStream_t st) {
+  const int prec = p->prec;
+  const std::vector<SkyBatch>& batches = gs.batches;
+  const size_t max_quads = gs.max_quads, max_spill = gs.max_spill, max_part = gs.max_part, max_abc = gs.max_abc;
+  const int max_sky = gs.max_sky;
+  Carve cv{(char*)ws};
+  double* d_ad = cv.take<double>(gs.sky_ad.size());
+  NodeDev* d_nodes = cv.take<NodeDev>(gs.ndev.size());
   struct SkySet {
     void* quads;
     double* abc;
@@ -451,14 +474,6 @@ fstat_status run_grid(fstat_plan_s* p, const fstat_node* nodes, int64_t n_nodes,
   d_spill[0] = cv.take<char>(max_spill);
   d_spill[1] = cv.take<char>(max_spill);
   MaxPartial* d_part = cv.take<MaxPartial>(max_part / sizeof(MaxPartial) + 1);
-  // stage descriptors
-  char* hp = (char*)p->pinned;
-  std::memcpy(hp, sky_ad.data(), sky_ad.size() * sizeof(double));
-  std::memcpy(hp + align_up(sky_ad.size() * sizeof(double)), ndev.data(), ndev.size() * sizeof(NodeDev));
-  HIP_TRY(hipMemcpyAsync(p->ws, hp, desc_bytes, hipMemcpyHostToDevice, st));
-  HIP_TRY(hipEventRecord(p->staged, st));
-  p->staged_pending = true;
-
   GridOut go{};
   go.mode = out->mode;
   go.k_lo = out->k_lo;
@@ -520,6 +535,23 @@ fstat_status run_grid(fstat_plan_s* p, const fstat_node* nodes, int64_t n_nodes,
   HIP_TRY(hipEventRecord(p->ev_join, s2));
   HIP_TRY(hipStreamWaitEvent(st, p->ev_join, 0));
   return FSTAT_OK;
+}
+
+// An eager grid call: schedule, stage the descriptors through pinned memory,
+// launch.
+fstat_status run_grid(fstat_plan_s* p, const fstat_node* nodes, int64_t n_nodes, const fstat_out* out,
+                      hipStream_t st) {
+  GridSched gs;
+  schedule_grid(p, nodes, n_nodes, gs);
+  fstat_status rc = ensure_ws(p, gs.need_ws);
+  if (rc != FSTAT_OK) return rc;
+  rc = ensure_pinned(p, gs.desc_bytes);
+  if (rc != FSTAT_OK) return rc;
+  pack_descriptors(gs, (char*)p->pinned);
+  HIP_TRY(hipMemcpyAsync(p->ws, p->pinned, gs.desc_bytes, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipEventRecord(p->staged, st));
+  p->staged_pending = true;
+  return launch_grid(p, gs, p->ws, out, st);
 }
 
 
@@ -755,8 +787,10 @@ fstat_status fstat_plan_info(fstat_plan_t p, int32_t seg, int64_t* n, int64_t* n
   return FSTAT_OK;
 }
 
-fstat_status fstat_grid(fstat_plan_t p, const fstat_node* nodes, int64_t n_nodes, const fstat_out* out,
-                        void* hip_stream) {
+}  // extern "C"
+
+namespace {
+fstat_status check_grid_args(const fstat_plan_s* p, const fstat_node* nodes, int64_t n_nodes, const fstat_out* out) {
   if (!p || !nodes || n_nodes <= 0 || !out) return FSTAT_EINVAL;
   if (n_nodes > (int64_t)INT32_MAX) return FSTAT_EUNSUPPORTED;
   if (out->mode < 0 || out->mode > 2) return FSTAT_EINVAL;
@@ -773,9 +807,78 @@ fstat_status fstat_grid(fstat_plan_t p, const fstat_node* nodes, int64_t n_nodes
       return FSTAT_EINVAL;
     if (out->k_hi > p->segs[nd.seg].dev.nfft / 2) return FSTAT_EINVAL;
   }
+  return FSTAT_OK;
+}
+
+void destroy_graph(fstat_graph_s* g) {
+  if (!g) return;
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  if (g->ws) (void)hipFree(g->ws);
+  delete g;
+}
+}  // namespace
+
+extern "C" {
+
+fstat_status fstat_grid(fstat_plan_t p, const fstat_node* nodes, int64_t n_nodes, const fstat_out* out,
+                        void* hip_stream) {
+  fstat_status rc = check_grid_args(p, nodes, n_nodes, out);
+  if (rc != FSTAT_OK) return rc;
   DeviceGuard guard(p->device);
   if (!guard.ok) return FSTAT_EDEVICE;
   return run_grid(p, nodes, n_nodes, out, (hipStream_t)hip_stream);
+}
+
+fstat_status fstat_graph_create(fstat_plan_t p, const fstat_node* nodes, int64_t n_nodes, const fstat_out* out,
+                                fstat_graph_t* g_out) {
+  if (!g_out) return FSTAT_EINVAL;
+  fstat_status rc = check_grid_args(p, nodes, n_nodes, out);
+  if (rc != FSTAT_OK) return rc;
+  DeviceGuard guard(p->device);
+  if (!guard.ok) return FSTAT_EDEVICE;
+  GridSched gs;
+  schedule_grid(p, nodes, n_nodes, gs);
+  fstat_graph_s* g = new (std::nothrow) fstat_graph_s;
+  if (!g) return FSTAT_ENOMEM;
+  g->plan = p;
+  std::vector<char> desc(gs.desc_bytes);
+  pack_descriptors(gs, desc.data());
+  hipStream_t cs = nullptr;
+  hipError_t e = hipMalloc(&g->ws, gs.need_ws);
+  if (e == hipSuccess) e = hipMemcpy(g->ws, desc.data(), gs.desc_bytes, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    p->capturing = true;
+    rc = launch_grid(p, gs, g->ws, out, cs);
+    p->capturing = false;
+    e = hipStreamEndCapture(cs, &g->graph);  // ends the capture whatever launch_grid returned
+    if (rc == FSTAT_OK && e == hipSuccess) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+  }
+  if (cs) (void)hipStreamDestroy(cs);
+  if (rc == FSTAT_OK && e != hipSuccess) rc = from_hip(e);
+  if (rc != FSTAT_OK) {
+    destroy_graph(g);
+    return rc;
+  }
+  *g_out = g;
+  return FSTAT_OK;
+}
+
+fstat_status fstat_graph_launch(fstat_graph_t g, void* hip_stream) {
+  if (!g || !g->exec) return FSTAT_EINVAL;
+  DeviceGuard guard(g->plan->device);
+  if (!guard.ok) return FSTAT_EDEVICE;
+  HIP_TRY(hipGraphLaunch(g->exec, (hipStream_t)hip_stream));
+  return FSTAT_OK;
+}
+
+void fstat_graph_destroy(fstat_graph_t g) {
+  if (!g) return;
+  DeviceGuard guard(g->plan->device);
+  (void)hipDeviceSynchronize();
+  destroy_graph(g);
 }
 
 fstat_status fstat_profile(fstat_plan_t p, int32_t enable) {

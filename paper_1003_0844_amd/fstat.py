@@ -75,9 +75,9 @@ class _Out(ctypes.Structure):
 NODE_DTYPE = np.dtype([("alpha", "<f8"), ("delta", "<f8"), ("fdot", "<f8"), ("seg", "<i4"), ("pad", "<i4")])
 CROSSING_DTYPE = np.dtype([("node", "<i8"), ("k", "<i8"), ("F", "<f8")])
 
-EXPORTS = ("fstat_plan", "fstat_grid", "fstat_eval", "fstat_adjoint", "fstat_grad", "fstat_plan_info",
-           "fstat_demod_series", "fstat_profile", "fstat_profile_read", "fstat_plan_schedule", "fstat_destroy",
-           "fstat_strerror")
+EXPORTS = ("fstat_plan", "fstat_grid", "fstat_graph_create", "fstat_graph_launch", "fstat_graph_destroy",
+           "fstat_eval", "fstat_adjoint", "fstat_grad", "fstat_plan_info", "fstat_demod_series", "fstat_profile",
+           "fstat_profile_read", "fstat_plan_schedule", "fstat_destroy", "fstat_strerror")
 K_SKY, K_PASS1, K_PASS2, K_OTHER = 0, 1, 2, 3
 
 _lib = None
@@ -93,6 +93,10 @@ def lib():
         vp, i64, i32, P = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.POINTER
         L.fstat_plan.argtypes = [P(_Segment), i32, P(_Detector), P(_Ephemeris), P(_Options), P(vp)]
         L.fstat_grid.argtypes = [vp, vp, i64, P(_Out), vp]
+        L.fstat_graph_create.argtypes = [vp, vp, i64, P(_Out), P(vp)]
+        L.fstat_graph_launch.argtypes = [vp, vp]
+        L.fstat_graph_destroy.argtypes = [vp]
+        L.fstat_graph_destroy.restype = None
         L.fstat_eval.argtypes = [vp, vp, vp, i64, vp, vp, vp]
         L.fstat_adjoint.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp]
         L.fstat_grad.argtypes = [vp, vp, vp, i64, vp, vp, vp]
@@ -105,7 +109,7 @@ def lib():
         L.fstat_strerror.argtypes = [i32]
         L.fstat_strerror.restype = ctypes.c_char_p
         L.fstat_destroy.restype = None
-        for name in ("fstat_plan", "fstat_grid", "fstat_eval", "fstat_adjoint", "fstat_grad", "fstat_plan_info",
+        for name in ("fstat_plan", "fstat_grid", "fstat_graph_create", "fstat_graph_launch", "fstat_eval", "fstat_adjoint", "fstat_grad", "fstat_plan_info",
                      "fstat_demod_series", "fstat_profile", "fstat_profile_read", "fstat_plan_schedule"):
             getattr(L, name).restype = i32
         _lib = L
@@ -301,6 +305,35 @@ class Plan:
         n = min(int(cnt.cpu().item()), rec.shape[0])
         return rec[:n].cpu().numpy().view(CROSSING_DTYPE).reshape(-1)
 
+    def _graph(self, nodes: np.ndarray, out: _Out, outputs: dict) -> "GridGraph":
+        nodes = np.ascontiguousarray(nodes, dtype=NODE_DTYPE)
+        h = ctypes.c_void_p()
+        _check(lib().fstat_graph_create(self._h, nodes.ctypes.data_as(ctypes.c_void_p), nodes.size,
+                                        ctypes.byref(out), ctypes.byref(h)), "fstat_graph_create")
+        return GridGraph(self, h, outputs)
+
+    def graph_map(self, nodes: np.ndarray, k_lo: int, k_hi: int, F: Optional[torch.Tensor] = None) -> "GridGraph":
+        """grid_map recorded as a graph: every launch() rewrites .outputs['F']."""
+        if F is None:
+            F = torch.empty((len(nodes), k_hi - k_lo), dtype=self.dtype, device=self._dev())
+        return self._graph(nodes, _Out(mode=OUT_MAP, k_lo=k_lo, k_hi=k_hi, F=F.data_ptr()), {"F": F})
+
+    def graph_max(self, nodes: np.ndarray, k_lo: int, k_hi: int) -> "GridGraph":
+        """grid_max recorded as a graph (outputs 'Fmax', 'kmax')."""
+        Fmax = torch.empty(len(nodes), dtype=self.dtype, device=self._dev())
+        kmax = torch.empty(len(nodes), dtype=torch.int64, device=self._dev())
+        out = _Out(mode=OUT_MAX, k_lo=k_lo, k_hi=k_hi, Fmax=Fmax.data_ptr(), kmax=kmax.data_ptr())
+        return self._graph(nodes, out, {"Fmax": Fmax, "kmax": kmax})
+
+    def graph_crossings(self, nodes: np.ndarray, k_lo: int, k_hi: int, threshold: float,
+                        max_crossings: int) -> "GridGraph":
+        """grid_crossings recorded as a graph (outputs 'rec', 'cnt')."""
+        rec = torch.empty((max(1, max_crossings), 3), dtype=torch.int64, device=self._dev())
+        cnt = torch.empty(1, dtype=torch.int64, device=self._dev())
+        out = _Out(mode=OUT_CROSSINGS, k_lo=k_lo, k_hi=k_hi, threshold=threshold, crossings=rec.data_ptr(),
+                   n_crossings=cnt.data_ptr(), max_crossings=max_crossings)
+        return self._graph(nodes, out, {"rec": rec, "cnt": cnt})
+
     def demod_series(self, node: np.ndarray) -> torch.Tensor:
         node = np.ascontiguousarray(np.asarray(node, dtype=NODE_DTYPE).reshape(1))
         n = self.info(int(node["seg"][0]))["n"]
@@ -346,6 +379,30 @@ class Plan:
         _check(lib().fstat_grad(self._h, _ptr(params), _ptr(seg), n, _ptr(F), _ptr(dF),
                                 _stream_ptr(self.device)), "fstat_grad")
         return F, dF
+
+
+class GridGraph:
+    """A recorded grid call (fstat_graph_create); launch() replays it on the
+    current stream.  Holds its plan and output tensors alive."""
+
+    def __init__(self, plan: Plan, handle: ctypes.c_void_p, outputs: dict):
+        self.plan = plan
+        self._h = handle
+        self.outputs = outputs
+
+    def launch(self):
+        _check(lib().fstat_graph_launch(self._h, _stream_ptr(self.plan.device)), "fstat_graph_launch")
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            lib().fstat_graph_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class FStatFn(torch.autograd.Function):

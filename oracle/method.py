@@ -114,6 +114,22 @@ def ssb_times(seg: Segment, alpha, delta, det, eph, tol=1e-12, max_iter=60):
     return tb0, t
 
 
+def ssb_positions(seg: Segment, alpha, delta, det, eph):
+    """Fractional sample positions u_j = t_j / dt of the barycentric grid, in
+    extended precision (numpy longdouble).  The FP64 solution of ssb_times is
+    refined by one more fixed-point step t <- t_b - phi_m(t) carried out in
+    extended precision: the step contracts the error by |phi_m'| ~ 1e-4, so
+    the result is exact to extended-precision rounding, whereas t_j / dt in
+    FP64 carries the rounding of an absolute time (~1e-10 s at 6 days), which
+    moves every interpolation weight by ~5e-10."""
+    L = np.longdouble
+    _, t = ssb_times(seg, alpha, delta, det, eph)
+    T0 = L(seg.t0)
+    tb = model.roemer_delay_ext(T0, alpha, delta, det, eph) + np.arange(seg.n, dtype=L) * L(seg.dt)
+    tx = tb - model.roemer_delay_ext(T0 + t.astype(L), alpha, delta, det, eph)
+    return tx / L(seg.dt)
+
+
 # --------------------------------------------------------------------------
 # Interpolation (Sec. VI A)
 # --------------------------------------------------------------------------
@@ -170,20 +186,22 @@ def interpolate(seg: Segment, u, mode):
     (t_b0 = phi_m(0) gives t_0 = 0), so the span test must not depend on the
     last bit of t: positions within SPAN_EPS samples of the span count as
     inside and are clamped onto it."""
-    u = np.asarray(u, dtype=np.float64)
+    u = np.asarray(u)
+    if u.dtype != np.longdouble:
+        u = u.astype(np.float64)
     n = seg.n
     valid = (u >= -SPAN_EPS) & (u <= n - 1 + SPAN_EPS)
     uu = np.where(valid, np.clip(u, 0.0, n - 1.0), 0.0)
-    xr = np.zeros_like(u)
-    dxdu = np.zeros_like(u)
+    xr = np.zeros(u.shape)
+    dxdu = np.zeros(u.shape)
     if mode == NEAREST:
         idx = np.floor(uu + 0.5).astype(np.int64)
         xr = np.where(valid, seg.xm[np.minimum(idx, n - 1)], 0.0)
         return xr, dxdu
     y, M = _upsampled(seg, mode)
-    v = 2.0 * uu
+    v = 2 * uu
     i = np.minimum(np.floor(v).astype(np.int64), 2 * n - 2)
-    s = v - i
+    s = (v - i).astype(np.float64)
     y0, y1 = y[i], y[i + 1]
     if mode == LINEAR_UP2:
         val = (1.0 - s) * y0 + s * y1
@@ -206,7 +224,7 @@ def interpolate(seg: Segment, u, mode):
 def resampled(seg: Segment, alpha, delta, det, eph, mode):
     """Everything the method needs on the uniform SSB grid for one sky point."""
     tb0, t = ssb_times(seg, alpha, delta, det, eph)
-    u = t / seg.dt
+    u = ssb_positions(seg, alpha, delta, det, eph)
     xr, dxdu = interpolate(seg, u, mode)
     a, b = model.amplitude_modulation(seg.t0 + t, alpha, delta, det, eph)
     pm = model.roemer_delay(seg.t0 + t, alpha, delta, det, eph)
@@ -354,7 +372,7 @@ def fstat_continuous(seg: Segment, params, det, eph, mode, grad=False):
     j = np.arange(n, dtype=np.float64)
     tb0, t = ssb_times(seg, alpha, delta, det, eph)
     T = seg.t0 + t
-    xr, dxdu = interpolate(seg, t / dt, mode)
+    xr, dxdu = interpolate(seg, ssb_positions(seg, alpha, delta, det, eph), mode)
     pm, pm_al, pm_de, pm_T = _roemer_partials(T, alpha, delta, det, eph)
     a, b, a_x, b_x, a_d, b_d = _ab_partials(T, alpha, delta, det, eph)
     cyc = demod_cycles(t, seg.t0, alpha, delta, seg.f_ref, fdot, det, eph) + f * j * dt

@@ -54,21 +54,25 @@ __device__ __forceinline__ void block_sums(double (&v)[NV], double* sh) {
   }
 }
 
-// interpolated x and dx/du at fractional sample position u
-__device__ __forceinline__ void interp_d(const SegDev& sg, double u, double& xr, double& dxdu) {
+// interpolated x and dx/du at the fractional sample position u = j + off
+// (integer j, small offset off = -dphi_m/dt: the weight carries the rounding of
+// off only)
+__device__ __forceinline__ void interp_d(const SegDev& sg, int64_t j, double off, double& xr, double& dxdu) {
   xr = 0.0;
   dxdu = 0.0;
   const int64_t n = sg.n;
-  if (!(u >= -SPAN_EPS && u <= (double)(n - 1) + SPAN_EPS)) return;
-  u = fmin(fmax(u, 0.0), (double)(n - 1));
+  const double lo = -(double)j, hi = (double)(n - 1 - j);
+  if (!(off >= lo - SPAN_EPS && off <= hi + SPAN_EPS)) return;
+  off = fmin(fmax(off, lo), hi);
   if (sg.interp == 0) {
-    xr = sg.x[(int64_t)floor(u + 0.5)];
+    xr = sg.x[j + (int64_t)floor(off + 0.5)];
     return;
   }
-  const double v = 2.0 * u;
-  int64_t i = (int64_t)floor(v);
+  const double w = 2.0 * off;
+  const double fl = floor(w);
+  int64_t i = 2 * j + (int64_t)fl;
   if (i > 2 * n - 2) i = 2 * n - 2;
-  const double s = v - (double)i;
+  const double s = w - fl;
   const double y0 = sg.y[i], y1 = sg.y[i + 1];
   if (sg.interp == 1) {
     xr = (1.0 - s) * y0 + s * y1;
@@ -110,7 +114,7 @@ k_eval(const SegDev* __restrict__ segs, int nseg, const int32_t* __restrict__ se
     const double t = ssb_to_detector(sg.geo, k, (double)j * sg.dt, e, dpm);
     const double pm = k.tb0 + dpm;
     double xr, dxdu;
-    interp_d(sg, t / sg.dt, xr, dxdu);
+    interp_d(sg, j, -dpm / sg.dt, xr, dxdu);
     double a, b;
     amp_ab(k, hour_angle(k, e.cth, e.sth), a, b);
     double cyc = sg.f_ref * dpm + c.fdot * (0.5 * t * t + pm * t) + c.f * ((double)j * sg.dt);
@@ -217,7 +221,7 @@ k_adjoint(const SegDev* __restrict__ segs, int nseg, const int32_t* __restrict__
     const double pm = k.tb0 + dpm;
     const Ephem e = ephem(sg.geo, t);  // absolute positions for the partials
     double xr, dxdu;
-    interp_d(sg, t / sg.dt, xr, dxdu);
+    interp_d(sg, j, -dpm / sg.dt, xr, dxdu);
     const AbPartials ab = ab_partials(k, hour_angle(k, ed.cth, ed.sth));
     const Partials pp = roemer_partials(sg, k, e);
     double cyc = sg.f_ref * dpm + c.fdot * (0.5 * t * t + pm * t) + c.f * jdt;

@@ -59,23 +59,28 @@ template <> struct DataPtrs<double> {
   static __device__ __forceinline__ const double* M(const SegDev& s) { return s.M; }
 };
 
-// x at fractional sample position u, 0 outside [0, N-1].
+// x at the fractional sample position u = j + off, 0 outside [0, N-1].  The
+// position is carried as the integer j plus the small offset off = -dphi_m/dt
+// (a few hundred samples at most), so the interpolation weight holds only the
+// rounding of off, not that of the absolute time j dt.
 // The first barycentric sample lands exactly on t = 0 (t_b0 = phi_m(0)); a
 // margin of SPAN_EPS samples keeps its last rounding bit from deciding whether
 // it is inside the data span.  Positions within the margin are clamped.
 template <typename T, int INTERP>
-__device__ __forceinline__ T interp_at(const SegDev& sg, double u) {
+__device__ __forceinline__ T interp_at(const SegDev& sg, int64_t j, double off) {
   const int64_t n = sg.n;
-  if (!(u >= -SPAN_EPS && u <= (double)(n - 1) + SPAN_EPS)) return (T)0;
-  u = fmin(fmax(u, 0.0), (double)(n - 1));
+  const double lo = -(double)j, hi = (double)(n - 1 - j);  // exact integers
+  if (!(off >= lo - SPAN_EPS && off <= hi + SPAN_EPS)) return (T)0;
+  off = fmin(fmax(off, lo), hi);
   if constexpr (INTERP == 0) {
-    const int64_t i = (int64_t)floor(u + 0.5);
+    const int64_t i = j + (int64_t)floor(off + 0.5);
     return DataPtrs<T>::x(sg)[i];
   } else {
-    const double v = 2.0 * u;
-    int64_t i = (int64_t)floor(v);
+    const double w = 2.0 * off;
+    const double fl = floor(w);
+    int64_t i = 2 * j + (int64_t)fl;
     if (i > 2 * n - 2) i = 2 * n - 2;
-    const T s = (T)(v - (double)i);
+    const T s = (T)(w - fl);
     const T* y = DataPtrs<T>::y(sg);
     const T y0 = y[i], y1 = y[i + 1];
     if constexpr (INTERP == 1) {
@@ -106,8 +111,8 @@ k_sky_prep(SegDev sg, const SkyConst* __restrict__ skies, Quad<T>* __restrict__ 
     if (j < sg.n) {
       EphemD e;
       double dpm;
-      const double t = ssb_to_detector(sg.geo, k, (double)j * sg.dt, e, dpm);
-      const T xr = interp_at<T, INTERP>(sg, t / sg.dt);
+      (void)ssb_to_detector(sg.geo, k, (double)j * sg.dt, e, dpm);
+      const T xr = interp_at<T, INTERP>(sg, j, -dpm / sg.dt);
       double a, b;
       amp_ab(k, hour_angle(k, e.cth, e.sth), a, b);
       double p = sg.f_ref * dpm;

@@ -744,11 +744,27 @@ fstat_status fstat_plan(const fstat_segment* segs, int32_t nseg, const fstat_det
   }
   if (opt->autotune) {
     for (int i = 0; i < nseg; ++i) {
-      fstat_status rc = tune_segment(p, i);
+      // segments of equal length and FFT size share one tuning run
+      int same = -1;
+      for (int j = 0; j < i && same < 0; ++j)
+        if (p->segs[j].dev.nfft == p->segs[i].dev.nfft && p->segs[j].dev.n == p->segs[i].dev.n) same = j;
+      fstat_status rc = FSTAT_OK;
+      if (same >= 0) {
+        apply_split(p->segs[i], opt->prec, p->segs[same].dev.C);
+        p->segs[i].node_cap = p->segs[same].node_cap;
+        rc = from_hip(make_split_tables(p->segs[i], opt->prec, nullptr));
+      } else {
+        rc = tune_segment(p, i);
+      }
       if (rc != FSTAT_OK) {
         destroy_plan(p);
         return rc;
       }
+    }
+    e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+      destroy_plan(p);
+      return from_hip(e);
     }
   }
   std::vector<SegDev> hs(nseg);

@@ -118,3 +118,44 @@ def segment_data(w: Workload, sigma: float = 1.0):
         sig = signal_params(g, w.n_signals, band,
                             snr=(6.0, 20.0) if w.n_signals > 8 else (10.0, 10.0))
     return g, x, sig
+
+
+@dataclass(frozen=True)
+class UnevenSegments:
+    """Many segments of different whole-day lengths with gaps, each with its
+    own small sky x spindown grid (dt = 0.5 s, nfft = nextpow2(2N))."""
+    name: str
+    n_seg: int
+    days: tuple          # inclusive range of the per-segment length in sidereal days
+    dt: float
+    max_gap_frac: float
+    n_sky: int           # per segment
+    n_fdot: int          # per segment
+    seed: int
+
+
+UNEVEN = UnevenSegments("256 segments of 1-6 days, dt=0.5 s, 0-10% gaps, 64 sky x 8 fdot each",
+                        256, (1, 6), 0.5, 0.10, 64, 8, 1002)
+
+
+def uneven_segments(u: UnevenSegments, sigma: float = 1.0):
+    """Per segment: (days, t0, noise x, gap mask), back to back in time, and the
+    grid of every segment as (alpha, delta, fdot) arrays.  Draw order: segment
+    lengths, noise, sky grids, gaps."""
+    g = rng(u.seed)
+    days = g.integers(u.days[0], u.days[1] + 1, size=u.n_seg)
+    t0 = np.concatenate([[0.0], np.cumsum(days[:-1]) * SIDEREAL_DAY])
+    xs = [white_noise(g, int(round(d * SIDEREAL_DAY / u.dt)), sigma) for d in days]
+    grids = []
+    fd = spindown_grid(u.n_fdot)
+    for _ in range(u.n_seg):
+        a, dl = sky_uniform(g, u.n_sky)
+        grids.append((np.repeat(a, u.n_fdot), np.repeat(dl, u.n_fdot), np.tile(fd, u.n_sky)))
+    masks = [gap_mask(g, len(x), u.dt, u.max_gap_frac) for x in xs]
+    return [(int(d), float(t), x, m) for d, t, x, m in zip(days, t0, xs, masks)], grids
+
+
+def candidate_offsets(seed: int, count: int, n_par: int = 4) -> np.ndarray:
+    """Random signs (+1/-1) per candidate and parameter, for candidates placed
+    half a cell away from a point in every parameter."""
+    return rng(seed).choice(np.array([-1.0, 1.0]), size=(count, n_par))

@@ -1,0 +1,237 @@
+"""The workloads at their full sizes, in the launch configuration the benchmark
+times (autotuned FP32 plan, two-stream pass pipeline), checked on sampled
+outputs against the FP64 oracle and by properties that hold at any size.
+
+  2-day all-sky grid:  N = 344656, nfft = 2^20, 1024 sky x 16 spindowns + 8 injections
+  uneven segments:     256 segments of 1-6 days with 0-10 % gaps, 64 x 8 nodes each, one graph
+  6-day grid:          N = 1033968, nfft = 2^21, 8192 x 32 nodes + 32 injections, FP32 vs FP64
+  refinement:          4096 candidates half a cell from the 1-day injection, 20 ascent steps
+"""
+import math
+import time
+
+import numpy as np
+import pytest
+import torch
+from scipy import stats
+
+from oracle import method, model
+from paper_1003_0844_amd import fstat, synth
+from tests.common import DET, EPH
+from tests.gpu_common import PREC_TOL, banner, f_error
+
+pytestmark = pytest.mark.gpu
+
+
+def _plan(specs, interp, prec, autotune=True, max_batch=0):
+    return fstat.Plan(specs, fstat.detector_spec(DET), fstat.ephemeris_spec(EPH), interp=interp, prec=prec,
+                      device=0, max_batch=max_batch, autotune=autotune)
+
+
+def _inject(x, dt, sigs, f_ref, t0=0.0, mask=None):
+    for p in sigs:
+        x = x + model.injection(len(x), dt, t0, p, f_ref, 1.0, DET, EPH, mask)
+    return x
+
+
+def _grid_nodes(g, w):
+    # same draw order as the benchmark: after noise and signal parameters
+    al, de = synth.sky_uniform(g, w.n_sky)
+    fd = synth.spindown_grid(w.n_fdot)
+    return fstat.nodes_array(np.repeat(al, w.n_fdot), np.repeat(de, w.n_fdot), np.tile(fd, w.n_sky))
+
+
+def _timed(fn):
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    r = fn()
+    torch.cuda.synchronize()
+    return r, time.perf_counter() - t
+
+
+def test_grid2d_full_grid_sampled_bins():
+    w = synth.GRID2D
+    g, x, sigs = synth.segment_data(w)
+    nodes = _grid_nodes(g, w)
+    banner("grid2d full grid", w.name)
+    x = _inject(x, w.dt, sigs, synth.F_REF)
+    inj = fstat.nodes_array([p["alpha"] for p in sigs], [p["delta"] for p in sigs], [p["fdot"] for p in sigs])
+    allnodes = np.concatenate([nodes, inj])
+    plan = _plan([fstat.SegmentSpec(x=x, dt=w.dt, n_days=w.days, nfft=w.nfft)], fstat.LINEAR_UP2, fstat.FP32)
+    half = w.nfft // 2
+    F, el = _timed(lambda: plan.grid_map(allnodes, 0, half))
+    print("grid2d: %d nodes in %.3f s (%.0f nodes/s), schedule %s" % (len(allnodes), el, len(allnodes) / el,
+                                                                      plan.schedule()), flush=True)
+    seg = method.Segment(x=x, dt=w.dt, n_days=w.days, f_ref=synth.F_REF, sigma2=1.0, nfft=w.nfft)
+    rng = np.random.default_rng(11)
+    rows = list(range(len(nodes), len(allnodes))) + list(rng.choice(len(nodes), 8, replace=False))
+    for r in rows:
+        Fr = F[r].cpu().numpy()
+        kk = [int(np.argmax(Fr))]
+        if r >= len(nodes):
+            k0 = int(round(sigs[r - len(nodes)]["f"] * w.nfft * w.dt))
+            kk += list(range(k0 - 3, k0 + 4))
+        k = np.unique(np.clip(np.r_[kk, rng.integers(0, half, 48)], 0, half - 1))
+        nd = allnodes[r]
+        ref = method.fstat_bins(seg, nd["fdot"], nd["alpha"], nd["delta"], DET, EPH, method.LINEAR_UP2, k=k)
+        err = f_error(Fr[k], ref)
+        assert err < PREC_TOL[fstat.FP32], (r, err)
+        if r >= len(nodes):
+            # the injection (SNR 10) stands out at its own node
+            assert 2 * Fr[kk[1:]].max() > 40.0, (r, 2 * Fr[kk[1:]].max())
+
+
+def test_uneven_segments_one_graph():
+    u = synth.UNEVEN
+    banner("uneven segments", u.name)
+    segs, grids = synth.uneven_segments(u)
+    specs = [fstat.SegmentSpec(x=x, dt=u.dt, n_days=d, t0=t0, mask=m) for d, t0, x, m in segs]
+    plan = _plan(specs, fstat.LINEAR_UP2, fstat.FP32)
+    nodes = np.concatenate([fstat.nodes_array(a, dl, fd, i) for i, (a, dl, fd) in enumerate(grids)])
+    # bins common to every segment: nfft = nextpow2(2N) of the shortest one
+    k_hi = min(1 << int(math.ceil(math.log2(2 * len(x)))) for _, _, x, _ in segs) // 2
+    graph = plan.graph_max(nodes, 0, k_hi)
+    _, el = _timed(graph.launch)
+    print("uneven: %d nodes over %d segments in one graph launch: %.3f s (%.0f nodes/s)"
+          % (len(nodes), len(segs), el, len(nodes) / el), flush=True)
+    Fmax = graph.outputs["Fmax"].cpu().numpy()
+    kmax = graph.outputs["kmax"].cpu().numpy()
+    # one sampled node per segment length
+    picked = {}
+    for i, (d, _, _, _) in enumerate(segs):
+        picked.setdefault(d, i)
+    rng = np.random.default_rng(5)
+    for d, si in sorted(picked.items()):
+        days, t0, x, m = segs[si]
+        seg = method.Segment(x=x, dt=u.dt, n_days=days, t0=t0, mask=m, f_ref=synth.F_REF, sigma2=1.0)
+        r = si * u.n_sky * u.n_fdot + int(rng.integers(0, u.n_sky * u.n_fdot))
+        nd = nodes[r]
+        ref = method.fstat_bins(seg, nd["fdot"], nd["alpha"], nd["delta"], DET, EPH, method.LINEAR_UP2,
+                                k=np.arange(k_hi), dft="fft")
+        # the maximum is unique as a value; its bin must be one where the
+        # oracle is within the tolerance of its own maximum
+        assert abs(Fmax[r] - ref.max()) / max(ref.max(), 1.0) < PREC_TOL[fstat.FP32], (d, Fmax[r], ref.max())
+        assert ref[kmax[r]] >= ref.max() - 2 * PREC_TOL[fstat.FP32] * max(ref.max(), 1.0), d
+    graph.close()
+
+
+def test_large6d_fp32_against_fp64_and_noise_law():
+    w = synth.LARGE6D
+    g, x0, sigs = synth.segment_data(w)
+    nodes = _grid_nodes(g, w)
+    banner("6-day grid", w.name)
+    x = _inject(x0, w.dt, sigs, synth.F_REF)
+    inj = fstat.nodes_array([p["alpha"] for p in sigs], [p["delta"] for p in sigs], [p["fdot"] for p in sigs])
+    allnodes = np.concatenate([nodes, inj])
+    spec = fstat.SegmentSpec(x=x, dt=w.dt, n_days=w.days, nfft=w.nfft)
+    half = w.nfft // 2
+    p32 = _plan([spec], fstat.LINEAR_UP2, fstat.FP32)
+    (F32, k32), el32 = _timed(lambda: p32.grid_max(allnodes, 0, half))
+    print("6-day FP32: %d nodes in %.3f s (%.0f nodes/s)" % (len(allnodes), el32, len(allnodes) / el32), flush=True)
+    sub = np.r_[np.random.default_rng(2).choice(len(nodes), 480, replace=False), np.arange(len(nodes), len(allnodes))]
+    p64 = _plan([spec], fstat.LINEAR_UP2, fstat.FP64, autotune=False, max_batch=1)
+    (F64, k64), el64 = _timed(lambda: p64.grid_max(allnodes[sub], 0, half))
+    print("6-day FP64 one node per launch: %d nodes in %.3f s (%.0f nodes/s)" % (len(sub), el64, len(sub) / el64),
+          flush=True)
+    F32s, k32s = F32.double().cpu().numpy()[sub], k32.cpu().numpy()[sub]
+    F64, k64 = F64.cpu().numpy(), k64.cpu().numpy()
+    assert f_error(F32s, F64) < PREC_TOL[fstat.FP32]
+    print("6-day FP32 vs FP64 per-node max: max rel err %.2e, argmax agree %d/%d"
+          % (f_error(F32s, F64), int(np.sum(k32s == k64)), len(sub)), flush=True)
+    # the strong injections (SNR >= 12) are the maximum of their own node, at their frequency
+    for i, p in enumerate(sigs):
+        if p["snr"] >= 12.0:
+            assert abs(int(k64[len(sub) - len(sigs) + i]) - p["f"] * w.nfft * w.dt) <= 3, (i, p)
+    # sampled bins of sampled nodes against the oracle, both precisions
+    seg = method.Segment(x=x, dt=w.dt, n_days=w.days, f_ref=synth.F_REF, sigma2=1.0, nfft=w.nfft)
+    rng = np.random.default_rng(9)
+    for r in [int(sub[0]), len(allnodes) - 1]:
+        nd = allnodes[r]
+        k = np.unique(np.r_[rng.integers(0, half, 32), int(k32[r].item())])
+        ref = method.fstat_bins(seg, nd["fdot"], nd["alpha"], nd["delta"], DET, EPH, method.LINEAR_UP2, k=k)
+        for plan, tol in ((p32, PREC_TOL[fstat.FP32]), (p64, PREC_TOL[fstat.FP64])):
+            Fm = plan.grid_map(allnodes[r:r + 1], 0, half)[0].cpu().numpy()
+            assert f_error(Fm[k], ref) < tol, (r, plan.prec, f_error(Fm[k], ref))
+    del p32, p64
+    torch.cuda.empty_cache()
+    # noise law of 2F: chi-square with 4 degrees of freedom, on pure noise with
+    # the cubic two-step resampling (whose power gain is flat across the band);
+    # one bin in three (the padding is 2.03x) of 8 nodes
+    pn = [_plan([fstat.SegmentSpec(x=x0, dt=w.dt, n_days=w.days, nfft=w.nfft)], fstat.CUBIC_UP2, prec,
+                autotune=False) for prec in (fstat.FP32, fstat.FP64)]
+    twoF = [2.0 * pl.grid_map(nodes[::4096][:8], 0, half)[:, ::3].double().cpu().numpy().ravel() for pl in pn]
+    for v, name in zip(twoF, ("FP32", "FP64")):
+        print("6-day noise 2F %s: mean %.4f var %.4f (chi2_4: 4, 8)" % (name, v.mean(), v.var()), flush=True)
+        # the cubic resampling's gain stays within about 1 % of unity across the band
+        assert abs(v.mean() - 4.0) < 0.06 and abs(v.var() - 8.0) < 0.4
+        ks = stats.kstest(v[::141][:20000], stats.chi2(4).cdf)
+        assert ks.statistic < 0.02, ks
+    assert abs(twoF[0].mean() / twoF[1].mean() - 1) < 1e-5
+
+
+def test_refinement_of_4096_candidates():
+    w = synth.TINY
+    g, x, sigs = synth.segment_data(w)
+    sig = sigs[0]
+    banner("refinement", w.name)
+    x = _inject(x, w.dt, [sig], synth.F_REF)
+    plan = _plan([fstat.SegmentSpec(x=x, dt=w.dt, n_days=w.days, nfft=w.nfft)], fstat.LINEAR_UP2, fstat.FP64,
+                 autotune=False)
+    seg = method.Segment(x=x, dt=w.dt, n_days=w.days, f_ref=synth.F_REF, sigma2=1.0, nfft=w.nfft)
+    T = w.n * w.dt
+    # cells: one Fourier bin, 1/T^2, and for the sky the offset whose orbital
+    # Doppler shift f_ref (v/c) dtheta is one Fourier bin: over one day the
+    # orbital velocity (v/c ~ 1e-4) dominates the sky resolution; the diurnal
+    # scale c / (2 pi f_ref R) ~ 0.017 rad holds only with the frequency re-fit
+    df = 1.0 / (w.nfft * w.dt)
+    v_c = model.AU * 2 * math.pi / model.YEAR / model.C_LIGHT
+    sky_cell = df / (synth.F_REF * v_c)
+    cell = np.array([df, 1.0 / T ** 2, sky_cell, sky_cell])
+    truth = np.array([sig["f"], sig["fdot"], sig["alpha"], sig["delta"]])
+    P0 = truth + 0.5 * cell * synth.candidate_offsets(1003, 4096)
+    P = torch.tensor(P0, dtype=torch.float64, device="cuda", requires_grad=True)
+    F = fstat.FStatFn.apply(P, plan)
+    (F.sum()).backward()
+    (F_g, dF), el = _timed(lambda: plan.grad(P.detach()))
+    print("refinement: F + gradient of 4096 candidates in %.4f s (%.0f candidates/s)" % (el, 4096 / el), flush=True)
+    assert torch.equal(F.detach(), F_g)
+    assert torch.allclose(P.grad, dF, rtol=1e-12, atol=0)
+    F0, dF = F_g.cpu().numpy(), dF.cpu().numpy()
+    # sampled candidates: oracle F and gradient, and central differences of the GPU F
+    for i in np.random.default_rng(4).choice(4096, 6, replace=False):
+        Fo, go = method.fstat_continuous(seg, P0[i], DET, EPH, method.LINEAR_UP2, grad=True)
+        assert abs(F0[i] - Fo) / max(Fo, 1.0) < 1e-10
+        scale = np.max(np.abs(go * cell))
+        assert np.max(np.abs((dF[i] - go) * cell)) < 1e-8 * scale, (i, dF[i], go)
+        # the linear interpolant has a kink every half sample: a step of h moves
+        # ~h/(half sample) of the positions across one, an error that shrinks
+        # linearly with h (1e-3 cell gives ~0.5 %), hence a small step
+        h = 1e-5 * cell
+        Pp = np.repeat(P0[i:i + 1], 8, axis=0)
+        for j in range(4):
+            Pp[2 * j, j] += h[j]
+            Pp[2 * j + 1, j] -= h[j]
+        Fp = plan.eval(torch.tensor(Pp, device="cuda"), want_state=False)[0].cpu().numpy()
+        fd = (Fp[0::2] - Fp[1::2]) / (2 * h)
+        assert np.max(np.abs((fd - dF[i]) * cell)) < 2e-4 * scale, (i, fd, dF[i])
+    # 20 ascent steps, theta <- theta + eta S^2 grad F with backtracking
+    S2 = torch.tensor(cell ** 2, device="cuda")
+    theta = torch.tensor(P0, device="cuda")
+    Fcur, gcur = plan.grad(theta)
+    eta = torch.full((4096, 1), 1.0 / max(float(Fcur.max().item()), 1.0), dtype=torch.float64, device="cuda")
+    for step in range(20):
+        trial = theta + eta * S2 * gcur
+        Ft, gt = plan.grad(trial)
+        ok = (Ft >= Fcur)[:, None]
+        theta = torch.where(ok, trial, theta)
+        Fcur = torch.where(ok[:, 0], Ft, Fcur)
+        gcur = torch.where(ok, gt, gcur)
+        eta = torch.where(ok, eta * 1.5, eta * 0.5)
+    Fend = Fcur.cpu().numpy()
+    d0 = np.linalg.norm((P0 - truth) / cell, axis=1)
+    d1 = np.linalg.norm((theta.cpu().numpy() - truth) / cell, axis=1)
+    print("refinement: median F %.2f -> %.2f, median distance %.3f -> %.3f cells"
+          % (np.median(F0), np.median(Fend), np.median(d0), np.median(d1)), flush=True)
+    assert np.all(Fend >= F0)
+    assert np.median(Fend) > np.median(F0)
+    assert np.median(d1) < np.median(d0)

@@ -24,6 +24,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, GB/s
+PROFILES = os.path.join(ROOT, "profiles")
+# sources that compile into the two FFT-pass kernels
+KERNEL_SOURCES = ("grid.hip", "fft_block.h", "cplx.h", "demod.h", "geometry.h", "internal.h")
 
 
 def parse():
@@ -67,6 +70,38 @@ def counters_run(args):
     print(json.dumps({"counters_run": "done", "grid_nodes": len(sub), "copy_bytes_each_way": 1 << 30,
                       "copy_ms": round(ms, 4), "copy_GBps_read_plus_write": round(2 * (1 << 30) / ms / 1e6, 1)}),
           flush=True)
+
+
+def kernel_digest() -> str:
+    """First 16 hex digits of the SHA-256 of the pass-kernel sources."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1003_0844_amd", "csrc", name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_record(kernel: str, sched: dict):
+    """HBM bytes per launch of a kernel from the committed counter summaries
+    (profiles/*traffic*.md, lines 'record: key=value ...'), or None when no
+    record matches the kernel, its schedule and the current kernel sources."""
+    digest = kernel_digest()
+    want = "C%d,batch%d" % (sched["C"], sched["batch"])
+    if not os.path.isdir(PROFILES):
+        return None
+    for name in sorted(os.listdir(PROFILES)):
+        if "traffic" not in name:
+            continue
+        with open(os.path.join(PROFILES, name)) as f:
+            for line in f:
+                line = line.strip().strip("`")
+                if not line.startswith("record:"):
+                    continue
+                kv = dict(t.split("=", 1) for t in line[len("record:"):].split() if "=" in t)
+                if kv.get("kernel") == kernel and kv.get("schedule") == want and kv.get("digest") == digest:
+                    return float(kv["bytes_per_launch"])
+    return None
 
 
 def log(*a):
@@ -182,7 +217,8 @@ def main():
         "config": {"workload": w.name + ", linear two-step resampling, full F map on bins [0, nfft/2)",
                    "nodes": nn, "n": w.n, "dt": w.dt, "nfft": w.nfft, "phase": "f64"},
         "roofline": {"bound": "hbm", "kernel": names[dom], "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic_record(names[dom], sched),
                      "avg_launch_us": round(1e3 * avg_ms, 2), "bytes_per_launch": bytes_per_launch,
                      "path_GBps": round(path_gbs, 1), "path_frac": round(path_gbs / HBM_PEAK_GBS, 4),
                      "path_bytes_per_node": round(step_bytes / nn)},

@@ -594,9 +594,11 @@ void cache_store(const TuneKey& k, int C, int batch) {
   std::fclose(f);
 }
 
-// Times every valid (C, batch) on a 4-sky x 16-spindown sample of the segment
-// (full map into a scratch buffer, two timed runs each, the faster counts)
-// and keeps the fastest.
+// Times every valid (C, batch) on an 8-sky x 16-spindown sample of the segment
+// (full map into a scratch buffer; one warm-up and three timed runs each, the
+// fastest counts) and keeps the fastest.  The default schedule is timed first
+// and another one replaces it only when at least 3 % faster, so that timing
+// noise does not pick a schedule that is no better.
 fstat_status tune_segment(fstat_plan_s* p, int si) {
   SegPlan& sp = p->segs[si];
   const int prec = p->prec;
@@ -610,20 +612,21 @@ fstat_status tune_segment(fstat_plan_s* p, int si) {
     HIP_TRY(hipDeviceSynchronize());
     return FSTAT_OK;
   }
-  std::vector<int> cands;
-  for (int c : {1024, 2048, 4096, sp.dev.C})
+  // the default first: split of choose_split, largest batch
+  std::vector<int> cands = {sp.dev.C};
+  for (int c : {4096, 2048, 1024})
     if (split_valid(prec, nfft, c) && std::find(cands.begin(), cands.end(), c) == cands.end()) cands.push_back(c);
   std::vector<int> batches;
   if (p->max_batch > 0) batches = {p->max_batch};
-  else if (prec == 0) batches = {8, 16, 32};
-  else batches = {2, 4, 8};
-  const int nsky = 4, nfd = 16;
+  else if (prec == 0) batches = {32, 16, 8};
+  else batches = {8, 4, 2};
+  const int nsky = 8, nfd = 16;
   std::vector<fstat_node> nodes(nsky * nfd);
   for (int s = 0; s < nsky; ++s)
     for (int f = 0; f < nfd; ++f) {
       fstat_node& nd = nodes[s * nfd + f];
-      nd.alpha = 0.4 + 1.5 * s;
-      nd.delta = -0.9 + 0.6 * s;
+      nd.alpha = 0.4 + 0.8 * s;
+      nd.delta = -1.2 + 0.3 * s;
       nd.fdot = -1e-9 * f / (nfd - 1);
       nd.seg = si;
       nd.pad = 0;
@@ -654,7 +657,7 @@ fstat_status tune_segment(fstat_plan_s* p, int si) {
     for (int b : batches) {
       sp.node_cap = b;
       double ms_min = 1e300;
-      for (int rep = 0; rep < 3 && rc == FSTAT_OK; ++rep) {
+      for (int rep = 0; rep < 4 && rc == FSTAT_OK; ++rep) {
         if ((e = hipEventRecord(ea, st)) != hipSuccess) rc = from_hip(e);
         if (rc == FSTAT_OK) rc = run_grid(p, nodes.data(), (int64_t)nodes.size(), &out, st);
         if (rc == FSTAT_OK && (e = hipEventRecord(eb, st)) != hipSuccess) rc = from_hip(e);
@@ -663,7 +666,7 @@ fstat_status tune_segment(fstat_plan_s* p, int si) {
         if (rc == FSTAT_OK && (e = hipEventElapsedTime(&ms, ea, eb)) != hipSuccess) rc = from_hip(e);
         if (rc == FSTAT_OK && rep > 0) ms_min = std::min(ms_min, (double)ms);  // rep 0 warms up
       }
-      if (rc == FSTAT_OK && ms_min < best_ms) {
+      if (rc == FSTAT_OK && (best_ms == 1e300 || ms_min < 0.97 * best_ms)) {
         best_ms = ms_min;
         best_C = cands[ci];
         best_b = b;

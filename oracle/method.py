@@ -290,6 +290,38 @@ def fstat_bins(seg: Segment, fdot, alpha, delta, det, eph, mode, k=None, dft="di
     return combine(Sa, Sb, A, B, C, seg.noise_var())
 
 
+def interbin(S_k, S_k1):
+    """Eq. (intbin): the DFT component half way between the Fourier bins k and
+    k + 1, approximated by (X(k+1) - X(k)) / sqrt(2) (interbinning, Sec. VI B)."""
+    return (np.asarray(S_k1) - np.asarray(S_k)) / math.sqrt(2.0)
+
+
+def fstat_bins_interbinned(seg: Segment, fdot, alpha, delta, det, eph, mode, k=None, dft="direct"):
+    """F at the Fourier bins k and at the half bins k + 1/2: Eq. (intbin)
+    applied to S_a and S_b, then the F combination.  Needs k + 1 <= nfft/2.
+    Returns (F at k, F at k + 1/2)."""
+    nfft = seg.fft_len
+    if k is None:
+        k = np.arange(nfft // 2, dtype=np.int64)
+    k = np.asarray(k, dtype=np.int64)
+    if k.size and (k.min() < 0 or k.max() + 1 > nfft // 2):
+        raise ValueError("bins k and k + 1 must lie in [0, nfft/2]")
+    kk = np.union1d(k, k + 1)
+    za, zb = demodulated(seg, fdot, alpha, delta, det, eph, mode)
+    if dft == "direct":
+        Sa, Sb = sums.dft_bins(za, nfft, kk), sums.dft_bins(zb, nfft, kk)
+    elif dft == "fft":
+        Sa, Sb = np.fft.fft(za, nfft)[kk], np.fft.fft(zb, nfft)[kk]
+    else:
+        raise ValueError(dft)
+    i0, i1 = np.searchsorted(kk, k), np.searchsorted(kk, k + 1)
+    A, B, C = abc(seg, alpha, delta, det, eph)
+    s2 = seg.noise_var()
+    F0 = combine(Sa[i0], Sb[i0], A, B, C, s2)
+    Fh = combine(interbin(Sa[i0], Sa[i1]), interbin(Sb[i0], Sb[i1]), A, B, C, s2)
+    return F0, Fh
+
+
 def fstat_exact(seg: Segment, f, fdot, alpha, delta, det, eph):
     """F by direct summation of Eqs. (Fab) on the detector samples, at the
     band-relative frequencies f (no resampling, no FFT)."""

@@ -38,6 +38,9 @@ def parse():
     ap.add_argument("--plain-nodes", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--interbin", action="store_true",
+                    help="the same grid with nfft = nextpow2(N) = 2^19 and interbinning (Eq. intbin): F at the "
+                         "Fourier bins and the half bins, as many output frequencies as the padded 2^20 map")
     ap.add_argument("--counters", action="store_true",
                     help="short run for hardware-counter collection: one grid call on the first 64 nodes "
                          "and a 1 GiB device copy of known size (the calibration of the byte counters)")
@@ -82,10 +85,11 @@ def kernel_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_record(kernel: str, sched: dict):
+def traffic_record(kernel: str, sched: dict, nfft: int, interbin: bool):
     """HBM bytes per launch of a kernel from the committed counter summaries
     (profiles/*traffic*.md, lines 'record: key=value ...'), or None when no
-    record matches the kernel, its schedule and the current kernel sources."""
+    record matches the kernel, its FFT length, schedule and output kind, and
+    the current kernel sources."""
     digest = kernel_digest()
     want = "C%d,batch%d" % (sched["C"], sched["batch"])
     if not os.path.isdir(PROFILES):
@@ -99,7 +103,8 @@ def traffic_record(kernel: str, sched: dict):
                 if not line.startswith("record:"):
                     continue
                 kv = dict(t.split("=", 1) for t in line[len("record:"):].split() if "=" in t)
-                if kv.get("kernel") == kernel and kv.get("schedule") == want and kv.get("digest") == digest:
+                if (kv.get("kernel") == kernel and kv.get("schedule") == want and kv.get("digest") == digest
+                        and kv.get("nfft") == str(nfft) and kv.get("interbin") == str(int(interbin))):
                     return float(kv["bytes_per_launch"])
     return None
 
@@ -119,27 +124,27 @@ def workload():
     return w, x, nodes
 
 
-def cpu_baseline(w, x, nodes, budget_s):
+def cpu_baseline(w, x, nodes, budget_s, nfft, ib):
     """The FP64 oracle (resampling method, FP64 numpy FFT for the DFT step) on
     the first nodes of the same grid, until the time budget is used."""
     import numpy as np
     from oracle import method, model
     from paper_1003_0844_amd import synth
     det, eph = model.default_detector(), model.Ephemeris()
-    seg = method.Segment(x=x, dt=w.dt, n_days=w.days, f_ref=synth.F_REF, sigma2=1.0, nfft=w.nfft)
+    seg = method.Segment(x=x, dt=w.dt, n_days=w.days, f_ref=synth.F_REF, sigma2=1.0, nfft=nfft)
     t0 = time.perf_counter()
     done = 0
     for nd in nodes:
-        method.fstat_bins(seg, float(nd["fdot"]), float(nd["alpha"]), float(nd["delta"]), det, eph,
-                          method.LINEAR_UP2, dft="fft")
+        fn = method.fstat_bins_interbinned if ib else method.fstat_bins
+        fn(seg, float(nd["fdot"]), float(nd["alpha"]), float(nd["delta"]), det, eph, method.LINEAR_UP2, dft="fft")
         done += 1
         if time.perf_counter() - t0 > budget_s:
             break
     el = time.perf_counter() - t0
     return {"value": done / el, "unit": "nodes/s", "cores": 1, "kind": "oracle",
-            "sample": "%d nodes of the same grid (full band, %d bins each), FP64 resampling method with "
+            "sample": "%d nodes of the same grid (full band, %d %s each), FP64 resampling method with "
                       "numpy FP64 FFT, one process, %.1f s incl. the segment's 2x upsampling"
-                      % (done, w.nfft // 2, el)}
+                      % (done, nfft // 2, "bins and half bins" if ib else "bins", el)}
 
 
 def main():
@@ -157,23 +162,26 @@ def main():
 
     w, x, nodes = workload()
     nn = len(nodes)
-    half = w.nfft // 2
-    log("workload: %s; building plan (autotuned)" % w.name)
-    plan = fstat.Plan([fstat.SegmentSpec(x=x, dt=w.dt, n_days=w.days, nfft=w.nfft)], fstat.default_detector(),
+    ib = bool(args.interbin)
+    nfft = (w.nfft // 2) if ib else w.nfft   # interbinning: nextpow2(N) instead of nextpow2(2N)
+    half = nfft // 2
+    width = 2 * half if ib else half
+    log("workload: %s%s; building plan (autotuned)" % (w.name, ", interbinned at nfft %d" % nfft if ib else ""))
+    plan = fstat.Plan([fstat.SegmentSpec(x=x, dt=w.dt, n_days=w.days, nfft=nfft)], fstat.default_detector(),
                       fstat.Ephemeris(), interp=fstat.LINEAR_UP2, prec=fstat.FP32, max_batch=args.max_batch,
                       autotune=True)
     sched = plan.schedule()
     log("schedule: %s" % sched)
-    F = torch.empty((nn, half), dtype=torch.float32, device="cuda")
+    F = torch.empty((nn, width), dtype=torch.float32, device="cuda")
     for i in range(args.warmup):
-        plan.grid_map(nodes, 0, half, F)
+        plan.grid_map(nodes, 0, half, F, interbin=ib)
         torch.cuda.synchronize()
         log("warmup step %d done" % i)
     plan.profile(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
-        plan.grid_map(nodes, 0, half, F)
+        plan.grid_map(nodes, 0, half, F, interbin=ib)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     log("timed %d steps: %.3f s" % (args.steps, el))
@@ -195,13 +203,13 @@ def main():
 
     # the plain path: all-FP64, one node per launch, on the first nodes of the grid
     sub = nodes[:args.plain_nodes]
-    plan64 = fstat.Plan([fstat.SegmentSpec(x=x, dt=w.dt, n_days=w.days, nfft=w.nfft)], fstat.default_detector(),
+    plan64 = fstat.Plan([fstat.SegmentSpec(x=x, dt=w.dt, n_days=w.days, nfft=nfft)], fstat.default_detector(),
                         fstat.Ephemeris(), interp=fstat.LINEAR_UP2, prec=fstat.FP64, max_batch=1)
-    F64 = torch.empty((len(sub), half), dtype=torch.float64, device="cuda")
-    plan64.grid_map(sub, 0, half, F64)
+    F64 = torch.empty((len(sub), width), dtype=torch.float64, device="cuda")
+    plan64.grid_map(sub, 0, half, F64, interbin=ib)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    plan64.grid_map(sub, 0, half, F64)
+    plan64.grid_map(sub, 0, half, F64, interbin=ib)
     torch.cuda.synchronize()
     plain = len(sub) / (time.perf_counter() - t1)
     diff = (F[:len(sub)].double() - F64).abs() / torch.clamp(F64.abs(), min=1.0)
@@ -214,11 +222,13 @@ def main():
         "value": round(value, 1), "unit": "nodes/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(step_ms, 3), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
-        "config": {"workload": w.name + ", linear two-step resampling, full F map on bins [0, nfft/2)",
-                   "nodes": nn, "n": w.n, "dt": w.dt, "nfft": w.nfft, "phase": "f64"},
+        "config": {"workload": (w.name.replace("nfft=2^20", "nfft=2^19") + ", linear two-step resampling, "
+                                "interbinned F map on bins and half bins of [0, nfft/2)") if ib else
+                               (w.name + ", linear two-step resampling, full F map on bins [0, nfft/2)"),
+                   "nodes": nn, "n": w.n, "dt": w.dt, "nfft": nfft, "interbin": ib, "phase": "f64"},
         "roofline": {"bound": "hbm", "kernel": names[dom], "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic_record(names[dom], sched),
+                     "traffic": traffic_record(names[dom], sched, nfft, ib),
                      "avg_launch_us": round(1e3 * avg_ms, 2), "bytes_per_launch": bytes_per_launch,
                      "path_GBps": round(path_gbs, 1), "path_frac": round(path_gbs / HBM_PEAK_GBS, 4),
                      "path_bytes_per_node": round(step_bytes / nn)},
@@ -232,7 +242,7 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(w, x, nodes, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(w, x, nodes, args.cpu_seconds, nfft, ib)
     print(json.dumps(out), flush=True)
 
 

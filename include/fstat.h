@@ -152,10 +152,16 @@ typedef struct {
  * for an FSTAT_FP32 plan and double for an FSTAT_FP64 plan. */
 typedef struct {
   int32_t mode;             /* FSTAT_OUT_MAP / _MAX / _CROSSINGS */
-  int32_t pad;
+  int32_t interbin;         /* 0: the Fourier bins k only.  1: also the half bins k + 1/2 by
+                               interbinning, Eq. (intbin) of Sec. VI B:
+                               S(k + 1/2) ~ (S(k+1) - S(k)) / sqrt(2) for S_a and S_b, then
+                               F as below.  Every output then covers 2 (k_hi - k_lo) points
+                               indexed 2k + h (h = 1 for k + 1/2): the map is
+                               [n_nodes][2 (k_hi - k_lo)], kmax and the crossings' k are in
+                               half-bin units.  Meant for nfft = nextpow2(n) (no padding). */
   int64_t k_lo, k_hi;       /* bins 0 <= k_lo < k_hi <= nfft/2 of every node's segment */
   double threshold;         /* mode CROSSINGS: report F > threshold */
-  void *F;                  /* device [n_nodes][k_hi - k_lo] (mode MAP) */
+  void *F;                  /* device [n_nodes][k_hi - k_lo] (mode MAP; twice as wide with interbin) */
   void *Fmax;               /* device [n_nodes] (mode MAX) */
   int64_t *kmax;            /* device [n_nodes] (mode MAX); ties go to the lowest bin */
   fstat_crossing *crossings;      /* device [max_crossings] (mode CROSSINGS), unordered */

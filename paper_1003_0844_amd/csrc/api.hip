@@ -476,6 +476,7 @@ fstat_status launch_grid(fstat_plan_s* p, const GridSched& gs, void* ws, const f
   MaxPartial* d_part = cv.take<MaxPartial>(max_part / sizeof(MaxPartial) + 1);
   GridOut go{};
   go.mode = out->mode;
+  go.interbin = out->interbin;
   go.k_lo = out->k_lo;
   go.k_hi = out->k_hi;
   go.threshold = out->threshold;
@@ -514,14 +515,16 @@ fstat_status launch_grid(fstat_plan_s* p, const GridSched& gs, void* ws, const f
       const NodeDev* dn = d_nodes + b.node0 + n0;
       void* spill = d_spill[chunk % 2];
       const double sbytes = 4.0 * er * (double)d.nfft * nn;
-      const double outb = out->mode == 0 ? er * (double)(out->k_hi - out->k_lo) * nn : 0.0;
+      const double ibf = out->interbin ? 2.0 : 1.0;  // outputs per bin
+      const double outb = out->mode == 0 ? ibf * er * (double)(out->k_hi - out->k_lo) * nn : 0.0;
+      const double p2read = out->interbin ? sbytes * (sp.B2 + 1) / sp.B2 : sbytes;
       if (chunk >= 2) HIP_TRY(hipStreamWaitEvent(st, p->ev_p2[chunk % 2], 0));
       HIP_TRY(timed(p, FSTAT_K_PASS1, sbytes + rec_bytes * nn / std::max(1, b.nnode / b.nsky), st, [&] {
         return fsk::grid_pass1(prec, d.C, d, ss.quads, qstride, ss.sky, dn, nn, sp.twC, sp.twlo, sp.twhi, spill, st);
       }));
       HIP_TRY(hipEventRecord(p->ev_p1[chunk % 2], st));
       HIP_TRY(hipStreamWaitEvent(s2, p->ev_p1[chunk % 2], 0));
-      HIP_TRY(timed(p, FSTAT_K_PASS2, sbytes + outb, s2, [&] {
+      HIP_TRY(timed(p, FSTAT_K_PASS2, p2read + outb, s2, [&] {
         return fsk::grid_pass2(prec, d.R, d, spill, dn, nn, ss.coef, sp.twR, go, d_part, s2);
       }));
       if (out->mode == 1)
@@ -813,6 +816,7 @@ fstat_status check_grid_args(const fstat_plan_s* p, const fstat_node* nodes, int
   if (!p || !nodes || n_nodes <= 0 || !out) return FSTAT_EINVAL;
   if (n_nodes > (int64_t)INT32_MAX) return FSTAT_EUNSUPPORTED;
   if (out->mode < 0 || out->mode > 2) return FSTAT_EINVAL;
+  if (out->interbin != 0 && out->interbin != 1) return FSTAT_EINVAL;
   if (out->k_lo < 0 || out->k_hi <= out->k_lo) return FSTAT_EINVAL;
   if (out->mode == 0 && !out->F) return FSTAT_EINVAL;
   if (out->mode == 1 && (!out->Fmax || !out->kmax)) return FSTAT_EINVAL;

@@ -213,7 +213,14 @@ __device__ __forceinline__ void fft_stage(lds_t<E>* __restrict__ lds, const TwF&
 #pragma unroll
     for (int m = 0; m < G::PER; ++m) {
       const int b = tid + m * BLOCK;
-      if (G::NB % BLOCK == 0 || b < G::NB) store(b / NCOL, b % NCOL, v[m], std::integral_constant<int, L / Rs>());
+      if (G::NB % BLOCK == 0 || b < G::NB) {
+        // store(i, col, v, STRIDE) or, when it takes one more argument, also the
+        // thread's butterfly slot m of the last stage
+        if constexpr (std::is_invocable_v<Store&, int, int, E (&)[Rs], std::integral_constant<int, L / Rs>, int>)
+          store(b / NCOL, b % NCOL, v[m], std::integral_constant<int, L / Rs>(), m);
+        else
+          store(b / NCOL, b % NCOL, v[m], std::integral_constant<int, L / Rs>());
+      }
     }
   } else {
     using G1 = StageShape<L, NCOL, BLOCK, S + 1>;

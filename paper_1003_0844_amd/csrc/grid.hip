@@ -152,6 +152,134 @@ k_pass2(SegDev sg, const Pair<T>* __restrict__ spill, const NodeDev* __restrict_
   }
 }
 
+constexpr int cmax(int a, int b) { return a > b ? a : b; }
+
+// Pass 2 with interbinning (Eq. intbin): F at the Fourier bins k and at the
+// half bins k + 1/2, with S(k + 1/2) ~ (S(k+1) - S(k)) / sqrt(2) for S_a and
+// S_b.  The workgroup transforms one column more than it owns, k2_0 + B2 (or
+// column 0 for the last block, whose outputs at k1 + 1 continue the band), so
+// that the right neighbour of every owned bin is local.  The final spectra
+// (rows k1 <= R/2) are staged in LDS; the epilogue reads each bin and its
+// neighbour from there.  Output index 2k + h, h = 1 for the half bin.
+template <typename T>
+constexpr int ib_block(int R) {
+  const int nb = (cfg_B2<T>(R) + 1) * R / 16;
+  const int b = (nb + 63) / 64 * 64;
+  return b > 1024 ? 1024 : b;
+}
+constexpr int ib_slots(int R, int ncol) { return cmax(lds_slots(R, ncol), 2 * (R / 2 + 1) * ncol); }
+
+template <typename T, int R, int MODE>
+__global__ void __launch_bounds__(ib_block<T>(R))
+k_pass2_ib(SegDev sg, const Pair<T>* __restrict__ spill, const NodeDev* __restrict__ nodes,
+           const SkyCoef* __restrict__ coef, const cpx<T>* __restrict__ twR, GridOut out,
+           MaxPartial* __restrict__ part) {
+  constexpr int B2 = cfg_B2<T>(R);
+  constexpr int NCOL = B2 + 1;
+  constexpr int BLOCK = ib_block<T>(R);
+  using GL = StageShape<R, NCOL, BLOCK, fft_nstages(R) - 1>;
+  __shared__ lds_t<Pair<T>> lds[ib_slots(R, NCOL)];
+  const int nd = blockIdx.y;
+  const int cb = xcd_local(blockIdx.x, gridDim.x);
+  const NodeDev node = nodes[nd];
+  const int C = sg.C;
+  const int k2_0 = cb * B2;
+  const bool wrap = k2_0 + B2 == C;
+  const int k2_x = wrap ? 0 : k2_0 + B2;
+  const Pair<T>* __restrict__ src = spill + (int64_t)nd * sg.nfft;
+  auto load = [&](int r, int col) -> Pair<T> { return src[(int64_t)r * C + (col < B2 ? k2_0 + col : k2_x)]; };
+  Pair<T> fin[GL::PER][GL::Rs];
+  auto keep = [&](int, int, auto& v, auto, int m) {
+#pragma unroll
+    for (int q = 0; q < GL::Rs; ++q) fin[m][q] = v[q];
+  };
+  block_fft<Pair<T>, R, NCOL, BLOCK, -1>(lds, twR, load, keep);
+  __syncthreads();  // every thread is past the last exchange
+  Pair<T>* __restrict__ stg = reinterpret_cast<Pair<T>*>(lds);  // [k1][col], k1 <= R/2
+#pragma unroll
+  for (int m = 0; m < GL::PER; ++m) {
+    const int b = (int)threadIdx.x + m * BLOCK;
+    if (GL::NB % BLOCK == 0 || b < GL::NB) {
+      const int col = b % NCOL;
+      const int i = b / NCOL;
+#pragma unroll
+      for (int q = 0; q < GL::Rs; ++q) {
+        const int k1 = i + q * (R / GL::Rs);
+        if (k1 <= R / 2) stg[k1 * NCOL + col] = fin[m][q];
+      }
+    }
+  }
+  __syncthreads();
+  const SkyCoef cf = coef[node.sky];
+  const T cB = (T)cf.cB, cA = (T)cf.cA, cC = (T)cf.cC;
+  const T rs2 = (T)0.70710678118654752440084436210485;
+  const int64_t klo = out.k_lo, khi = out.k_hi;
+  double best = -1.0;
+  int64_t bestk = INT64_MAX;
+  // explicit fused operations: every output mode rounds identically
+  auto fcomb = [&](const cpx<T>& a, const cpx<T>& b) -> T {
+    const T pa = fma(a.x, a.x, a.y * a.y);
+    const T pb = fma(b.x, b.x, b.y * b.y);
+    const T re = fma(a.x, b.x, a.y * b.y);
+    return fma(cB, pa, fma(cA, pb, -(cC * re)));
+  };
+  auto emit = [&](int64_t k, int h, T F) {
+    const int64_t kh = 2 * k + h;
+    if constexpr (MODE == 0) {
+      ((T*)out.F)[(int64_t)node.row * 2 * (khi - klo) + (kh - 2 * klo)] = F;
+    } else if constexpr (MODE == 1) {
+      const double f = (double)F;
+      if (f > best || (f == best && kh < bestk)) {
+        best = f;
+        bestk = kh;
+      }
+    } else {
+      if ((double)F > out.threshold) {
+        const unsigned long long n = atomicAdd(out.n_xing, 1ull);
+        if ((int64_t)n < out.max_xing) ((Crossing*)out.xing)[n] = Crossing{node.row, kh, (double)F};
+      }
+    }
+  };
+  for (int o = threadIdx.x; o < (R / 2) * B2; o += BLOCK) {
+    const int col = o % B2;
+    const int k1 = o / B2;
+    const int64_t k = (int64_t)C * k1 + k2_0 + col;
+    if (k < klo || k >= khi) continue;
+    const Pair<T> s0 = stg[k1 * NCOL + col];
+    const Pair<T> s1 = col + 1 < B2 ? stg[k1 * NCOL + col + 1] : stg[(wrap ? k1 + 1 : k1) * NCOL + B2];
+    const cpx<T> ha{(s1.a.x - s0.a.x) * rs2, (s1.a.y - s0.a.y) * rs2};
+    const cpx<T> hb{(s1.b.x - s0.b.x) * rs2, (s1.b.y - s0.b.y) * rs2};
+    emit(k, 0, fcomb(s0.a, s0.b));
+    emit(k, 1, fcomb(ha, hb));
+  }
+  if constexpr (MODE == 1) {
+    __shared__ double sf[BLOCK / 64];
+    __shared__ int64_t sk[BLOCK / 64];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const double f2 = __shfl_down(best, o, 64);
+      const int64_t k2 = __shfl_down(bestk, o, 64);
+      if (f2 > best || (f2 == best && k2 < bestk)) {
+        best = f2;
+        bestk = k2;
+      }
+    }
+    if ((threadIdx.x & 63) == 0) {
+      sf[threadIdx.x >> 6] = best;
+      sk[threadIdx.x >> 6] = bestk;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      for (int w = 1; w < BLOCK / 64; ++w)
+        if (sf[w] > best || (sf[w] == best && sk[w] < bestk)) {
+          best = sf[w];
+          bestk = sk[w];
+        }
+      part[(int64_t)nd * gridDim.x + cb] = MaxPartial{best, bestk};
+    }
+  }
+}
+
 template <typename T>
 __global__ void k_max_finalize(const MaxPartial* __restrict__ part, int nparts, const NodeDev* __restrict__ nodes,
                                int nnodes, T* __restrict__ Fmax, int64_t* __restrict__ kmax) {
@@ -197,12 +325,16 @@ template <typename T, int MODE>
 hipError_t launch_pass2_mode(int R, const SegDev& seg, const void* spill, const NodeDev* nodes, int nnodes,
                              const SkyCoef* coef, const void* twR, const GridOut& out, MaxPartial* part,
                              hipStream_t st) {
-#define P2(RR)                                                                                      \
-  case RR: {                                                                                        \
-    constexpr int B2 = cfg_B2<T>(RR);                                                               \
-    dim3 grid(seg.C / B2, nnodes);                                                                  \
-    hipLaunchKernelGGL((k_pass2<T, RR, MODE>), grid, dim3(cfg_block(B2 * RR / 16)), 0, st, seg,     \
-                       (const Pair<T>*)spill, nodes, coef, (const cpx<T>*)twR, out, part);          \
+#define P2(RR)                                                                                        \
+  case RR: {                                                                                          \
+    constexpr int B2 = cfg_B2<T>(RR);                                                                 \
+    dim3 grid(seg.C / B2, nnodes);                                                                    \
+    if (out.interbin)                                                                                 \
+      hipLaunchKernelGGL((k_pass2_ib<T, RR, MODE>), grid, dim3(ib_block<T>(RR)), 0, st, seg,          \
+                         (const Pair<T>*)spill, nodes, coef, (const cpx<T>*)twR, out, part);          \
+    else                                                                                              \
+      hipLaunchKernelGGL((k_pass2<T, RR, MODE>), grid, dim3(cfg_block(B2 * RR / 16)), 0, st, seg,     \
+                         (const Pair<T>*)spill, nodes, coef, (const cpx<T>*)twR, out, part);          \
   } break;
   switch (R) {
     P2(16) P2(32) P2(64) P2(128) P2(256) P2(512) P2(1024)

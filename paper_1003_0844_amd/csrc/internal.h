@@ -51,6 +51,7 @@ struct SegDev {
 
 struct GridOut {
   int32_t mode;        // 0 map, 1 per-node max, 2 crossings
+  int32_t interbin;    // 1: also the half bins k + 1/2 (output index 2k + h)
   int64_t k_lo, k_hi;
   double threshold;
   void* F;             // mode 0: [rows][k_hi-k_lo] of T

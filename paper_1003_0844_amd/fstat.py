@@ -66,7 +66,7 @@ class _Options(ctypes.Structure):
 
 
 class _Out(ctypes.Structure):
-    _fields_ = [("mode", ctypes.c_int32), ("pad", ctypes.c_int32), ("k_lo", ctypes.c_int64),
+    _fields_ = [("mode", ctypes.c_int32), ("interbin", ctypes.c_int32), ("k_lo", ctypes.c_int64),
                 ("k_hi", ctypes.c_int64), ("threshold", ctypes.c_double), ("F", ctypes.c_void_p),
                 ("Fmax", ctypes.c_void_p), ("kmax", ctypes.c_void_p), ("crossings", ctypes.c_void_p),
                 ("n_crossings", ctypes.c_void_p), ("max_crossings", ctypes.c_int64)]
@@ -273,28 +273,36 @@ class Plan:
         _check(lib().fstat_grid(self._h, nodes.ctypes.data_as(ctypes.c_void_p), nodes.size, ctypes.byref(out),
                                 _stream_ptr(self.device)), "fstat_grid")
 
-    def grid_map(self, nodes: np.ndarray, k_lo: int, k_hi: int, F: Optional[torch.Tensor] = None) -> torch.Tensor:
-        """F on bins [k_lo, k_hi) of every node: tensor [n_nodes, k_hi - k_lo]."""
+    def grid_map(self, nodes: np.ndarray, k_lo: int, k_hi: int, F: Optional[torch.Tensor] = None,
+                 interbin: bool = False) -> torch.Tensor:
+        """F on bins [k_lo, k_hi) of every node: tensor [n_nodes, k_hi - k_lo]; with
+        interbin, [n_nodes, 2 (k_hi - k_lo)]: F at k and k + 1/2 interleaved."""
+        w = (2 if interbin else 1) * (k_hi - k_lo)
         if F is None:
-            F = torch.empty((len(nodes), k_hi - k_lo), dtype=self.dtype, device=self._dev())
-        out = _Out(mode=OUT_MAP, k_lo=k_lo, k_hi=k_hi, F=F.data_ptr())
+            F = torch.empty((len(nodes), w), dtype=self.dtype, device=self._dev())
+        out = _Out(mode=OUT_MAP, interbin=int(interbin), k_lo=k_lo, k_hi=k_hi, F=F.data_ptr())
         self._grid(nodes, out)
         return F
 
-    def grid_max(self, nodes: np.ndarray, k_lo: int, k_hi: int):
-        """Per node: (max F on [k_lo, k_hi), its bin)."""
+    def grid_max(self, nodes: np.ndarray, k_lo: int, k_hi: int, interbin: bool = False):
+        """Per node: (max F on [k_lo, k_hi), its bin; with interbin the half bins
+        count too and the bin is in half-bin units 2k + h)."""
         Fmax = torch.empty(len(nodes), dtype=self.dtype, device=self._dev())
         kmax = torch.empty(len(nodes), dtype=torch.int64, device=self._dev())
-        out = _Out(mode=OUT_MAX, k_lo=k_lo, k_hi=k_hi, Fmax=Fmax.data_ptr(), kmax=kmax.data_ptr())
+        out = _Out(mode=OUT_MAX, interbin=int(interbin), k_lo=k_lo, k_hi=k_hi, Fmax=Fmax.data_ptr(),
+                   kmax=kmax.data_ptr())
         self._grid(nodes, out)
         return Fmax, kmax
 
-    def grid_crossings(self, nodes: np.ndarray, k_lo: int, k_hi: int, threshold: float, max_crossings: int):
+    def grid_crossings(self, nodes: np.ndarray, k_lo: int, k_hi: int, threshold: float, max_crossings: int,
+                       interbin: bool = False):
         """All (node, bin, F) with F > threshold, unordered: a device buffer of
-        fstat_crossing records (int64 [max, 3] words) and the total count."""
+        fstat_crossing records (int64 [max, 3] words) and the total count
+        (with interbin the bin is in half-bin units 2k + h)."""
         rec = torch.empty((max(1, max_crossings), 3), dtype=torch.int64, device=self._dev())
         cnt = torch.empty(1, dtype=torch.int64, device=self._dev())
-        out = _Out(mode=OUT_CROSSINGS, k_lo=k_lo, k_hi=k_hi, threshold=threshold, crossings=rec.data_ptr(),
+        out = _Out(mode=OUT_CROSSINGS, interbin=int(interbin), k_lo=k_lo, k_hi=k_hi, threshold=threshold,
+                   crossings=rec.data_ptr(),
                    n_crossings=cnt.data_ptr(), max_crossings=max_crossings)
         self._grid(nodes, out)
         return rec, cnt
@@ -312,26 +320,30 @@ class Plan:
                                         ctypes.byref(out), ctypes.byref(h)), "fstat_graph_create")
         return GridGraph(self, h, outputs)
 
-    def graph_map(self, nodes: np.ndarray, k_lo: int, k_hi: int, F: Optional[torch.Tensor] = None) -> "GridGraph":
+    def graph_map(self, nodes: np.ndarray, k_lo: int, k_hi: int, F: Optional[torch.Tensor] = None,
+                  interbin: bool = False) -> "GridGraph":
         """grid_map recorded as a graph: every launch() rewrites .outputs['F']."""
+        w = (2 if interbin else 1) * (k_hi - k_lo)
         if F is None:
-            F = torch.empty((len(nodes), k_hi - k_lo), dtype=self.dtype, device=self._dev())
-        return self._graph(nodes, _Out(mode=OUT_MAP, k_lo=k_lo, k_hi=k_hi, F=F.data_ptr()), {"F": F})
+            F = torch.empty((len(nodes), w), dtype=self.dtype, device=self._dev())
+        out = _Out(mode=OUT_MAP, interbin=int(interbin), k_lo=k_lo, k_hi=k_hi, F=F.data_ptr())
+        return self._graph(nodes, out, {"F": F})
 
-    def graph_max(self, nodes: np.ndarray, k_lo: int, k_hi: int) -> "GridGraph":
+    def graph_max(self, nodes: np.ndarray, k_lo: int, k_hi: int, interbin: bool = False) -> "GridGraph":
         """grid_max recorded as a graph (outputs 'Fmax', 'kmax')."""
         Fmax = torch.empty(len(nodes), dtype=self.dtype, device=self._dev())
         kmax = torch.empty(len(nodes), dtype=torch.int64, device=self._dev())
-        out = _Out(mode=OUT_MAX, k_lo=k_lo, k_hi=k_hi, Fmax=Fmax.data_ptr(), kmax=kmax.data_ptr())
+        out = _Out(mode=OUT_MAX, interbin=int(interbin), k_lo=k_lo, k_hi=k_hi, Fmax=Fmax.data_ptr(),
+                   kmax=kmax.data_ptr())
         return self._graph(nodes, out, {"Fmax": Fmax, "kmax": kmax})
 
     def graph_crossings(self, nodes: np.ndarray, k_lo: int, k_hi: int, threshold: float,
-                        max_crossings: int) -> "GridGraph":
+                        max_crossings: int, interbin: bool = False) -> "GridGraph":
         """grid_crossings recorded as a graph (outputs 'rec', 'cnt')."""
         rec = torch.empty((max(1, max_crossings), 3), dtype=torch.int64, device=self._dev())
         cnt = torch.empty(1, dtype=torch.int64, device=self._dev())
-        out = _Out(mode=OUT_CROSSINGS, k_lo=k_lo, k_hi=k_hi, threshold=threshold, crossings=rec.data_ptr(),
-                   n_crossings=cnt.data_ptr(), max_crossings=max_crossings)
+        out = _Out(mode=OUT_CROSSINGS, interbin=int(interbin), k_lo=k_lo, k_hi=k_hi, threshold=threshold,
+                   crossings=rec.data_ptr(), n_crossings=cnt.data_ptr(), max_crossings=max_crossings)
         return self._graph(nodes, out, {"rec": rec, "cnt": cnt})
 
     def demod_series(self, node: np.ndarray) -> torch.Tensor:

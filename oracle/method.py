@@ -322,6 +322,88 @@ def fstat_bins_interbinned(seg: Segment, fdot, alpha, delta, det, eph, mode, k=N
     return F0, Fh
 
 
+# --------------------------------------------------------------------------
+# Amplitude parameters (Sec. III, Eqs. ampone, amle0, h0iota)
+# --------------------------------------------------------------------------
+def amplitudes_from_parameters(h0, cosi, psi, phi0):
+    """The four amplitudes of Eq. (ampone) from h0, cos(iota), psi, phi0, with
+    h0+ = h0 (1 + cos^2 iota)/2 and h0x = h0 cos(iota) (Eq. h0iota)."""
+    hp, hx = 0.5 * h0 * (1.0 + cosi * cosi), h0 * cosi
+    c2, s2, cp, sp_ = math.cos(2 * psi), math.sin(2 * psi), math.cos(phi0), math.sin(phi0)
+    return np.array([hp * c2 * cp - hx * s2 * sp_,
+                     hp * s2 * cp + hx * c2 * sp_,
+                     -hp * c2 * sp_ - hx * s2 * cp,
+                     -hp * s2 * sp_ + hx * c2 * cp])
+
+
+def parameters_from_amplitudes(Ab):
+    """Inversion of Eq. (ampone), then of Eq. (h0iota).  With
+    z1 = Ab1 + i Ab2 and z2 = Ab4 - i Ab3, Eq. (ampone) reads
+    z1 + z2 = (h0+ + h0x) e^{i(2 psi + phi0)} and
+    z1 - z2 = (h0+ - h0x) e^{i(2 psi - phi0)}, so h0+ +- h0x = |z1 +- z2| (the
+    unique solution of the paper's A = h0+^2 + h0x^2, D = h0+ h0x with h0+ > 0)
+    and the two arguments give psi and phi0 with their quadrants (the paper's
+    tan(2 phi0), tan(4 psi) relations fix them only modulo pi/2 and pi/4).
+    Then h0 = h0+ + sqrt(h0+^2 - h0x^2) and cos iota = h0x / h0.
+    Convention: psi in [0, pi/2), phi0 in [0, 2 pi) ((psi + pi/2, phi0 + pi)
+    gives the same amplitudes); for cos iota = +-1 only 2 psi +- phi0 is
+    determined and the argument of the vanishing combination is taken as 0.
+    Returns (h0, cos iota, psi, phi0)."""
+    a1, a2, a3, a4 = (float(v) for v in Ab)
+    zp = complex(a1 + a4, a2 - a3)
+    zm = complex(a1 - a4, a2 + a3)
+    sp_, sm = abs(zp), abs(zm)
+    hp, hx = 0.5 * (sp_ + sm), 0.5 * (sp_ - sm)
+    h0 = hp + math.sqrt(sp_ * sm)
+    cosi = hx / h0 if h0 > 0 else 0.0
+    ap = math.atan2(zp.imag, zp.real) if sp_ > 0 else 0.0
+    am = math.atan2(zm.imag, zm.real) if sm > 0 else 0.0
+    psi = 0.25 * (ap + am)
+    phi0 = 0.5 * (ap - am)
+    shift = math.floor(psi / (math.pi / 2))
+    psi -= shift * (math.pi / 2)
+    phi0 -= shift * math.pi
+    return h0, cosi, psi, phi0 % (2 * math.pi)
+
+
+def amplitude_estimates(Sa, Sb, A, B, C, theta0, sin_zeta=1.0):
+    """ML estimators of the amplitudes (Eq. amle0) from the correlations S_a,
+    S_b of the resampling method.  theta0 restores the phase common to S_a and
+    S_b that the method leaves out (reading R-f0): S_true = S e^{-i theta0}.
+    With h1..h4 = a cos, b cos, a sin, b sin of the phase, the normal equations
+    are [A C; C B] (A1, A2) = 2 Re(S_a, S_b) and the same for (A3, A4) with
+    -Im; C = 0 gives Eq. (amle0).  Returns the amplitudes divided by sin(zeta)."""
+    rot = complex(math.cos(theta0), -math.sin(theta0))
+    sa, sb = complex(Sa) * rot, complex(Sb) * rot
+    det_ = A * B - C * C
+    inv = np.array([[B, -C], [-C, A]]) / det_
+    a12 = 2.0 * inv @ np.array([sa.real, sb.real])
+    a34 = 2.0 * inv @ np.array([-sa.imag, -sb.imag])
+    return np.array([a12[0], a12[1], a34[0], a34[1]]) / sin_zeta
+
+
+def estimate_parameters(seg: Segment, params, det, eph, mode):
+    """Amplitude estimates and (h0, cos iota, psi, phi0) at continuous
+    (f, fdot, alpha, delta) by the resampling method (the second step of the
+    ML estimation, Sec. III)."""
+    f, fdot, alpha, delta = (float(v) for v in params)
+    n, dt = seg.n, seg.dt
+    j = np.arange(n, dtype=np.float64)
+    _, t = ssb_times(seg, alpha, delta, det, eph)
+    T = seg.t0 + t
+    xr, _ = interpolate(seg, ssb_positions(seg, alpha, delta, det, eph), mode)
+    a, b = model.amplitude_modulation(T, alpha, delta, det, eph)
+    cyc = demod_cycles(t, seg.t0, alpha, delta, seg.f_ref, fdot, det, eph) + f * j * dt
+    e = np.exp(-2j * math.pi * (cyc - np.round(cyc)))
+    Sa, Sb = np.sum(xr * a * e), np.sum(xr * b * e)
+    A, B, C = abc(seg, alpha, delta, det, eph)
+    L = np.longdouble
+    turns = (L(seg.f_ref) + L(f)) * model.roemer_delay_ext(L(seg.t0), alpha, delta, det, eph)
+    theta0 = 2.0 * math.pi * float(turns - np.round(turns))
+    Ab = amplitude_estimates(Sa, Sb, A, B, C, theta0, math.sin(det.zeta))
+    return Ab, parameters_from_amplitudes(Ab)
+
+
 def fstat_exact(seg: Segment, f, fdot, alpha, delta, det, eph):
     """F by direct summation of Eqs. (Fab) on the detector samples, at the
     band-relative frequencies f (no resampling, no FFT)."""

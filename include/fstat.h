@@ -221,6 +221,21 @@ fstat_status fstat_eval(fstat_plan_t p, const double *params, const int32_t *seg
 fstat_status fstat_adjoint(fstat_plan_t p, const double *params, const int32_t *seg, int64_t n,
                            const double *state, const double *gF, double *dparams, void *hip_stream);
 
+/* Second step of the maximum-likelihood estimation (Sec. III): at the
+ * candidates' (f, fdot, alpha, delta), the estimators of the four amplitudes
+ * (Eq. amle0; with gaps, the 2 x 2 normal equations in A, B, C that reduce to it
+ * when C = 0) and their inversion to h0, cos(iota), psi, phi0 (Eqs. ampone,
+ * h0iota).  The phase 2 pi (f_ref + f) phi_m(0) that F does not need is
+ * restored, so phi0 refers to the signal phase of Eq. (pha3) at t = 0.
+ *   state: device [n][FSTAT_STATE] from fstat_eval with the same params
+ *   out:   device [n][8]: the amplitudes A1..A4 of Eq. (ampone) (the data's
+ *          amplitudes divided by sin zeta), h0, cos(iota), psi in [0, pi/2),
+ *          phi0 in [0, 2 pi) ((psi + pi/2, phi0 + pi) describes the same wave;
+ *          for cos(iota) = +-1 only 2 psi +- phi0 is determined).
+ * Invalid segment indices give NaN rows. */
+fstat_status fstat_amplitudes(fstat_plan_t p, const double *params, const int32_t *seg, int64_t n,
+                              const double *state, double *out, void *hip_stream);
+
 /* Convenience: F and (if dF != NULL) dF/d(f, fdot, alpha, delta), device [n] and [n][4]. */
 fstat_status fstat_grad(fstat_plan_t p, const double *params, const int32_t *seg, int64_t n, double *F,
                         double *dF, void *hip_stream);

@@ -214,6 +214,7 @@ fstat_status build_segment(const fstat_segment& s, const fstat_detector& det, co
   d.geo.sth0 = std::sin(TWO_PI * d.geo.sid_c0);
   d.geo.ceps = std::cos(eph.obliquity_rad);
   d.geo.seps = std::sin(eph.obliquity_rad);
+  d.geo.sin_zeta = std::sin(det.zeta_rad);
   d.geo.s2g = std::sin(2.0 * det.gamma_rad);
   d.geo.c2g = std::cos(2.0 * det.gamma_rad);
   d.geo.sl = std::sin(det.lat_rad);
@@ -954,6 +955,15 @@ fstat_status fstat_adjoint(fstat_plan_t p, const double* params, const int32_t* 
   DeviceGuard guard(p->device);
   if (!guard.ok) return FSTAT_EDEVICE;
   return from_hip(fsk::grad_adjoint(p->d_segs, (int)p->segs.size(), seg, params, n, state, gF, dparams, (hipStream_t)hip_stream));
+}
+
+fstat_status fstat_amplitudes(fstat_plan_t p, const double* params, const int32_t* seg, int64_t n,
+                              const double* state, double* out, void* hip_stream) {
+  if (!p || !params || n <= 0 || !state || !out) return FSTAT_EINVAL;
+  if (n > (int64_t)INT32_MAX) return FSTAT_EUNSUPPORTED;
+  DeviceGuard guard(p->device);
+  if (!guard.ok) return FSTAT_EDEVICE;
+  return from_hip(fsk::amplitudes(p->d_segs, (int)p->segs.size(), seg, params, n, state, out, (hipStream_t)hip_stream));
 }
 
 fstat_status fstat_grad(fstat_plan_t p, const double* params, const int32_t* seg, int64_t n, double* F, double* dF,

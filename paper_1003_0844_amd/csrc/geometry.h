@@ -28,6 +28,7 @@ struct SegGeo {
   double sl, cl;      // sin, cos of latitude
   double s2l, c2l;    // sin, cos of 2 latitude
   double cth0, sth0;  // cos, sin of the sidereal angle at t = 0
+  double sin_zeta;    // sin of the angle between the arms (scales the amplitudes)
 };
 
 // Everything about one sky position that the per-sample loops need.

@@ -269,9 +269,76 @@ k_adjoint(const SegDev* __restrict__ segs, int nseg, const int32_t* __restrict__
   }
 }
 
+// Second step of the ML estimation (Sec. III): the amplitudes of Eq. (ampone)
+// from the correlations of k_eval, and their inversion.  One thread per
+// candidate.  The correlations leave out the phase 2 pi (f_ref + f) phi_m(0)
+// common to S_a and S_b; it is restored first.  With h1..h4 = a cos, b cos,
+// a sin, b sin of the phase the normal equations are
+//   [A C; C B] (A1, A2) = 2 (Re S_a, Re S_b),  [A C; C B] (A3, A4) = -2 (Im S_a, Im S_b)
+// (Eq. amle0 when C = 0).  Inversion: z1 = A1 + i A2, z2 = A4 - i A3 satisfy
+// z1 +- z2 = (h0+ +- h0x) e^{i(2 psi +- phi0)}; h0 = h0+ + sqrt(h0+^2 - h0x^2),
+// cos iota = h0x / h0 (Eq. h0iota).  psi in [0, pi/2), phi0 in [0, 2 pi).
+__global__ void k_amplitudes(const SegDev* __restrict__ segs, int nseg, const int32_t* __restrict__ segi,
+                             const double* __restrict__ params, const double* __restrict__ state, int64_t n,
+                             double* __restrict__ out) {
+  const int64_t ci = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (ci >= n) return;
+  double* o = out + 8 * ci;
+  const int si = segi ? segi[ci] : 0;
+  if (si < 0 || si >= nseg) {
+    for (int q = 0; q < 8; ++q) o[q] = __builtin_nan("");
+    return;
+  }
+  const SegDev sg = segs[si];
+  const Cand c{params[4 * ci], params[4 * ci + 1], params[4 * ci + 2], params[4 * ci + 3]};
+  SkyConst k;
+  setup_sky(sg, c, k);
+  const double* st = state + FSTATE * ci;
+  double turns = (sg.f_ref + c.f) * k.tb0;
+  turns -= rint(turns);
+  double sn, cs;
+  sincospi(2.0 * turns, &sn, &cs);
+  // S e^{-i theta0}
+  const double sar = st[0] * cs + st[1] * sn, sai = st[1] * cs - st[0] * sn;
+  const double sbr = st[2] * cs + st[3] * sn, sbi = st[3] * cs - st[2] * sn;
+  const double A = st[4], B = st[5], C = st[6];
+  const double w = 2.0 / ((A * B - C * C) * sg.geo.sin_zeta);
+  const double a1 = w * (B * sar - C * sbr), a2 = w * (A * sbr - C * sar);
+  const double a3 = -w * (B * sai - C * sbi), a4 = -w * (A * sbi - C * sai);
+  const double zpr = a1 + a4, zpi = a2 - a3, zmr = a1 - a4, zmi = a2 + a3;
+  const double mp = sqrt(zpr * zpr + zpi * zpi), mm = sqrt(zmr * zmr + zmi * zmi);
+  const double hp = 0.5 * (mp + mm), hx = 0.5 * (mp - mm);
+  const double h0 = hp + sqrt(mp * mm);
+  const double ap = mp > 0.0 ? atan2(zpi, zpr) : 0.0;
+  const double am = mm > 0.0 ? atan2(zmi, zmr) : 0.0;
+  const double half_pi = 1.5707963267948966192313216916398;
+  double psi = 0.25 * (ap + am), phi0 = 0.5 * (ap - am);
+  const double shift = floor(psi / half_pi);
+  psi -= shift * half_pi;
+  phi0 -= shift * 2.0 * half_pi;
+  phi0 -= floor(phi0 / (4.0 * half_pi)) * (4.0 * half_pi);
+  o[0] = a1;
+  o[1] = a2;
+  o[2] = a3;
+  o[3] = a4;
+  o[4] = h0;
+  o[5] = h0 > 0.0 ? hx / h0 : 0.0;
+  o[6] = psi;
+  o[7] = phi0;
+}
+
 }  // namespace
 
 namespace fsk {
+
+hipError_t amplitudes(const SegDev* d_segs, int nseg, const int32_t* d_seg, const double* d_params, int64_t n,
+                      const double* d_state, double* d_out, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_amplitudes, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, st, d_segs, nseg, d_seg,
+                     d_params, d_state, n, d_out);
+  return hipGetLastError();
+}
+
 
 hipError_t grad_forward(const SegDev* d_segs, int nseg, const int32_t* d_seg, const double* d_params, int64_t n,
                         double* d_F, double* d_state, hipStream_t st) {

@@ -113,4 +113,6 @@ hipError_t grad_forward(const SegDev* d_segs, int nseg, const int32_t* d_seg, co
                         double* d_F, double* d_state, hipStream_t st);
 hipError_t grad_adjoint(const SegDev* d_segs, int nseg, const int32_t* d_seg, const double* d_params, int64_t n,
                         const double* d_state, const double* d_gF, double* d_dp, hipStream_t st);
+hipError_t amplitudes(const SegDev* d_segs, int nseg, const int32_t* d_seg, const double* d_params, int64_t n,
+                      const double* d_state, double* d_out, hipStream_t st);
 }  // namespace fsk

@@ -76,7 +76,8 @@ NODE_DTYPE = np.dtype([("alpha", "<f8"), ("delta", "<f8"), ("fdot", "<f8"), ("se
 CROSSING_DTYPE = np.dtype([("node", "<i8"), ("k", "<i8"), ("F", "<f8")])
 
 EXPORTS = ("fstat_plan", "fstat_grid", "fstat_graph_create", "fstat_graph_launch", "fstat_graph_destroy",
-           "fstat_eval", "fstat_adjoint", "fstat_grad", "fstat_plan_info", "fstat_demod_series", "fstat_profile",
+           "fstat_eval", "fstat_adjoint", "fstat_amplitudes", "fstat_grad", "fstat_plan_info", "fstat_demod_series",
+           "fstat_profile",
            "fstat_profile_read", "fstat_plan_schedule", "fstat_destroy", "fstat_strerror")
 K_SKY, K_PASS1, K_PASS2, K_OTHER = 0, 1, 2, 3
 
@@ -100,6 +101,7 @@ def lib():
         L.fstat_eval.argtypes = [vp, vp, vp, i64, vp, vp, vp]
         L.fstat_adjoint.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp]
         L.fstat_grad.argtypes = [vp, vp, vp, i64, vp, vp, vp]
+        L.fstat_amplitudes.argtypes = [vp, vp, vp, i64, vp, vp, vp]
         L.fstat_plan_info.argtypes = [vp, i32, P(i64), P(i64), P(ctypes.c_double), P(i32), P(i32)]
         L.fstat_demod_series.argtypes = [vp, vp, vp, vp]
         L.fstat_profile.argtypes = [vp, i32]
@@ -109,7 +111,8 @@ def lib():
         L.fstat_strerror.argtypes = [i32]
         L.fstat_strerror.restype = ctypes.c_char_p
         L.fstat_destroy.restype = None
-        for name in ("fstat_plan", "fstat_grid", "fstat_graph_create", "fstat_graph_launch", "fstat_eval", "fstat_adjoint", "fstat_grad", "fstat_plan_info",
+        for name in ("fstat_plan", "fstat_grid", "fstat_graph_create", "fstat_graph_launch", "fstat_amplitudes",
+                     "fstat_eval", "fstat_adjoint", "fstat_grad", "fstat_plan_info",
                      "fstat_demod_series", "fstat_profile", "fstat_profile_read", "fstat_plan_schedule"):
             getattr(L, name).restype = i32
         _lib = L
@@ -382,6 +385,16 @@ class Plan:
         _check(lib().fstat_adjoint(self._h, _ptr(params), _ptr(seg), n, _ptr(state.contiguous()), _ptr(gF),
                                    _ptr(dp), _stream_ptr(self.device)), "fstat_adjoint")
         return dp
+
+    def amplitudes(self, params: torch.Tensor, seg: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """[n, 8]: amplitudes A1..A4, h0, cos(iota), psi, phi0 at the candidates
+        (fstat_eval, then fstat_amplitudes)."""
+        params, seg = self._params(params, seg)
+        _, state = self.eval(params, seg)
+        out = torch.empty((params.shape[0], 8), dtype=torch.float64, device=self._dev())
+        _check(lib().fstat_amplitudes(self._h, _ptr(params), _ptr(seg), params.shape[0], _ptr(state), _ptr(out),
+                                      _stream_ptr(self.device)), "fstat_amplitudes")
+        return out
 
     def grad(self, params: torch.Tensor, seg: Optional[torch.Tensor] = None):
         params, seg = self._params(params, seg)

@@ -1,0 +1,83 @@
+"""Amplitude estimation on the GPU (fstat_amplitudes, Sec. III: Eqs. amle0,
+ampone, h0iota) against the oracle's second step of the ML estimation."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import method, model
+from paper_1003_0844_amd import fstat, synth
+from tests.common import DET, EPH, one_signal, small_segment
+from tests.gpu_common import banner, make_plan
+
+pytestmark = pytest.mark.gpu
+
+
+def _angle_err(a, b, period):
+    d = (a - b) % period
+    return min(d, period - d)
+
+
+def _case(seed, gaps, noise):
+    dt = 26.0
+    n = int(round(2 * synth.SIDEREAL_DAY / dt))
+    mask = synth.gap_mask(synth.rng(90 + seed), n, dt, 0.1) if gaps else None
+    sig = one_signal(seed, band=1 / (2 * dt), snr=30.0)
+    seg = small_segment(days=2, dt=dt, seed=seed, signal=sig, noise=noise, mask=mask)
+    return seg, sig
+
+
+@pytest.mark.parametrize("gaps,noise", [(False, False), (True, False), (True, True)])
+def test_amplitudes_match_oracle(gaps, noise):
+    seg, sig = _case(7, gaps, noise)
+    banner("amplitudes", "gaps", gaps, "noise", noise)
+    plan = make_plan([seg], method.CUBIC_UP2, fstat.FP64)
+    truth = np.array([sig["f"], sig["fdot"], sig["alpha"], sig["delta"]])
+    cell = np.array([1 / (seg.fft_len * seg.dt), 1 / (seg.n * seg.dt) ** 2, 2e-4, 2e-4])
+    P = truth + 0.3 * cell * np.array([[0, 0, 0, 0], [1, -1, 1, -1], [-1, 1, 1, 1]])
+    out = plan.amplitudes(torch.tensor(P, device="cuda")).cpu().numpy()
+    for i in range(P.shape[0]):
+        Ab, (h0, ci, psi, phi0) = method.estimate_parameters(seg, P[i], DET, EPH, method.CUBIC_UP2)
+        scale = np.max(np.abs(Ab))
+        assert np.max(np.abs(out[i, :4] - Ab)) < 1e-9 * scale, (i, out[i, :4], Ab)
+        assert abs(out[i, 4] - h0) < 1e-9 * h0 and abs(out[i, 5] - ci) < 1e-8
+        assert _angle_err(out[i, 6], psi, math.pi / 2) < 1e-7 and _angle_err(out[i, 7], phi0, 2 * math.pi) < 1e-7
+
+
+def test_injected_parameters_come_back():
+    # noise-free data at the true intrinsic parameters: the injection's
+    # amplitude parameters up to the method's own error
+    seg, sig = _case(8, True, False)
+    banner("amplitudes round trip")
+    plan = make_plan([seg], method.CUBIC_UP2, fstat.FP64)
+    t = np.arange(seg.n) * seg.dt
+    h1 = model.signal(t, 0.0, sig["f"], sig["fdot"], sig["alpha"], sig["delta"], 1.0, sig["cosi"], sig["psi"],
+                      sig["phi0"], seg.f_ref, DET, EPH)
+    m = seg.mask.astype(float)
+    h0 = sig["snr"] / math.sqrt(np.sum(m * h1 * h1) / seg.sigma2)
+    out = plan.amplitudes(torch.tensor([[sig["f"], sig["fdot"], sig["alpha"], sig["delta"]]],
+                                       dtype=torch.float64, device="cuda")).cpu().numpy()[0]
+    # the amplitudes carry the method's own error (cubic two-step resampling,
+    # the dropped Jacobian: ~0.1 %); psi and phi0 amplify it by about
+    # 1 / (1 - |cos iota|) (only 2 psi +- phi0 is defined for circular waves)
+    want = method.amplitudes_from_parameters(h0, sig["cosi"], sig["psi"], sig["phi0"])
+    assert np.max(np.abs(out[:4] - want)) < 2e-3 * np.max(np.abs(want))
+    assert abs(out[4] / h0 - 1) < 3e-3 and abs(out[5] - sig["cosi"]) < 5e-3
+    # psi and phi0 come from the arguments of z1 +- z2 (z1 = A1 + i A2,
+    # z2 = A4 - i A3), the smaller of which has modulus h0 (1 - |cos iota|)^2 / 2:
+    # an amplitude error e moves its argument by up to 2 e over that modulus
+    e_amp = 2e-3 * np.max(np.abs(want))
+    tol = 2.0 * e_amp / (0.5 * h0 * (1.0 - abs(sig["cosi"])) ** 2)
+    assert _angle_err(out[6], sig["psi"] % (math.pi / 2), math.pi / 2) < tol
+    ph_true = sig["phi0"] + (math.pi if (sig["psi"] % math.pi) >= math.pi / 2 else 0.0)
+    assert _angle_err(out[7], ph_true % (2 * math.pi), 2 * math.pi) < tol
+
+
+def test_invalid_segment_gives_nan_rows():
+    seg, sig = _case(9, False, True)
+    banner("amplitudes invalid segment")
+    plan = make_plan([seg], method.LINEAR_UP2, fstat.FP64)
+    P = torch.tensor([[sig["f"], sig["fdot"], sig["alpha"], sig["delta"]]] * 2, dtype=torch.float64, device="cuda")
+    out = plan.amplitudes(P, seg=torch.tensor([0, 5], dtype=torch.int32)).cpu().numpy()
+    assert np.all(np.isfinite(out[0])) and np.all(np.isnan(out[1]))

@@ -404,6 +404,83 @@ def estimate_parameters(seg: Segment, params, det, eph, mode):
     return Ab, parameters_from_amplitudes(Ab)
 
 
+# --------------------------------------------------------------------------
+# Candidate selection and fine search (Secs. III B, VI C)
+# --------------------------------------------------------------------------
+def false_alarm_cell(F0):
+    """Eq. (PF): probability that F exceeds F0 in one cell without a signal."""
+    return (1.0 + F0) * math.exp(-F0)
+
+
+def threshold(alpha, n_cells):
+    """F0 with false-alarm probability alpha over n_cells cells: Eq. (FP)
+    solved for F0 by bisection on Eq. (PF).  P_F = 1 - (1 - alpha)^(1/N_c) is
+    formed as -expm1(log1p(-alpha)/N_c): the direct form cancels for small alpha
+    and large N_c."""
+    pf = -math.expm1(math.log1p(-alpha) / n_cells)
+    lo, hi = 0.0, 1.0
+    while false_alarm_cell(hi) > pf:
+        hi *= 2.0
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if false_alarm_cell(mid) > pf:
+            lo = mid
+        else:
+            hi = mid
+    return 0.5 * (lo + hi)
+
+
+def nelder_mead_max(fun, x0, scale, tol, max_evals):
+    """Maximum of fun by the Nelder-Mead simplex method (Nelder & Mead 1965;
+    reflection 1, expansion 2, contraction 1/2, shrink 1/2) on -fun in the
+    coordinates u = (x - x0)/scale, from the simplex x0 + unit steps; stops
+    when all vertices are within tol of the best one (max norm, in u) or after
+    max_evals evaluations.  Returns (x, fun(x), evaluations)."""
+    x0 = np.asarray(x0, dtype=np.float64)
+    scale = np.asarray(scale, dtype=np.float64)
+    dim = x0.size
+    nev = [0]
+
+    def g(u):
+        nev[0] += 1
+        return -fun(x0 + u * scale)
+
+    V = [np.zeros(dim)] + [np.eye(dim)[i] for i in range(dim)]
+    G = [g(v) for v in V]
+    while nev[0] < max_evals:
+        order = sorted(range(dim + 1), key=lambda i: G[i])
+        V = [V[i] for i in order]
+        G = [G[i] for i in order]
+        if max(np.max(np.abs(v - V[0])) for v in V[1:]) < tol:
+            break
+        cen = np.mean(V[:-1], axis=0)
+        xr = cen + (cen - V[-1])
+        gr = g(xr)
+        if gr < G[0]:
+            xe = cen + 2.0 * (xr - cen)
+            ge = g(xe)
+            V[-1], G[-1] = (xe, ge) if ge < gr else (xr, gr)
+        elif gr < G[-2]:
+            V[-1], G[-1] = xr, gr
+        else:
+            if gr < G[-1]:
+                xc = cen + 0.5 * (xr - cen)
+                gc = g(xc)
+                ok = gc <= gr
+            else:
+                xc = cen + 0.5 * (V[-1] - cen)
+                gc = g(xc)
+                ok = gc < G[-1]
+            if ok:
+                V[-1], G[-1] = xc, gc
+            else:
+                for i in range(1, dim + 1):
+                    V[i] = V[0] + 0.5 * (V[i] - V[0])
+                    G[i] = g(V[i])
+    b = int(np.argmin(G))
+    return x0 + V[b] * scale, -G[b], nev[0]
+
+
 def fstat_exact(seg: Segment, f, fdot, alpha, delta, det, eph):
     """F by direct summation of Eqs. (Fab) on the detector samples, at the
     band-relative frequencies f (no resampling, no FFT)."""

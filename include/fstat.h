@@ -236,6 +236,40 @@ fstat_status fstat_adjoint(fstat_plan_t p, const double *params, const int32_t *
 fstat_status fstat_amplitudes(fstat_plan_t p, const double *params, const int32_t *seg, int64_t n,
                               const double *state, double *out, void *hip_stream);
 
+/* F at the candidates' (f, fdot, alpha, delta) without resampling: Eqs. (OS)-(Fab)
+ * summed directly on the detector samples t_i = i dt with the phase of Eq. (pha3)
+ * (less the heterodyne) at the detector time, as the paper's fine search
+ * evaluates it (Sec. VII).  FP64.  params, seg, F as for fstat_eval. */
+fstat_status fstat_eval_exact(fstat_plan_t p, const double *params, const int32_t *seg, int64_t n, double *F,
+                              void *hip_stream);
+
+/* Fine search (Sec. VI C): from each candidate, a Nelder-Mead simplex search for
+ * the maximum of F over (f, fdot, alpha, delta), all candidates in one launch
+ * (one workgroup each).  Coordinates are scaled by scale[] (the initial simplex is
+ * the start plus one step scale[d] along each axis); the search stops when every
+ * vertex lies within tol scale units (per axis) of the best one, or after
+ * max_evals evaluations of F.  Coefficients: reflection 1, expansion 2,
+ * contraction 1/2, shrink 1/2. */
+typedef struct {
+  double scale[4];    /* > 0, in the units of f (Hz), fdot (Hz/s), alpha, delta (rad) */
+  double tol;         /* > 0, in scale units */
+  int32_t max_evals;  /* 5 .. 100000 */
+  int32_t exact;      /* 1: F of fstat_eval_exact; 0: F of fstat_eval (resampling method) */
+} fstat_refine_options;
+/*   params:     device [n][4] starting points (e.g. the coarse-grid maxima)
+ *   params_out: device [n][4] best vertex;  F_out: device [n] its F
+ *   evals_out:  device [n] F evaluations used, or NULL.  Invalid segments give NaN. */
+fstat_status fstat_refine(fstat_plan_t p, const double *params, const int32_t *seg, int64_t n,
+                          const fstat_refine_options *opt, double *params_out, double *F_out, int32_t *evals_out,
+                          void *hip_stream);
+
+/* Detection threshold F0 for a false-alarm probability alpha over n_cells
+ * independent cells: inverts Eq. (FP), alpha = 1 - (1 - P_F(F0))^N_c, with
+ * P_F(F0) = (1 + F0) e^{-F0} of Eq. (PF) (2F chi-square with 4 degrees of
+ * freedom).  Host computation; 0 < alpha < 1, n_cells >= 1.  The expected number
+ * of false alarms is N_c P_F(F0) (Eq. NF). */
+fstat_status fstat_threshold(double alpha, double n_cells, double *F0);
+
 /* Convenience: F and (if dF != NULL) dF/d(f, fdot, alpha, delta), device [n] and [n][4]. */
 fstat_status fstat_grad(fstat_plan_t p, const double *params, const int32_t *seg, int64_t n, double *F,
                         double *dF, void *hip_stream);

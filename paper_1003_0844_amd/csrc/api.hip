@@ -957,6 +957,50 @@ fstat_status fstat_adjoint(fstat_plan_t p, const double* params, const int32_t* 
   return from_hip(fsk::grad_adjoint(p->d_segs, (int)p->segs.size(), seg, params, n, state, gF, dparams, (hipStream_t)hip_stream));
 }
 
+fstat_status fstat_eval_exact(fstat_plan_t p, const double* params, const int32_t* seg, int64_t n, double* F,
+                              void* hip_stream) {
+  if (!p || !params || n <= 0 || !F) return FSTAT_EINVAL;
+  if (n > (int64_t)INT32_MAX) return FSTAT_EUNSUPPORTED;
+  DeviceGuard guard(p->device);
+  if (!guard.ok) return FSTAT_EDEVICE;
+  return from_hip(fsk::eval_exact(p->d_segs, (int)p->segs.size(), seg, params, n, F, (hipStream_t)hip_stream));
+}
+
+fstat_status fstat_refine(fstat_plan_t p, const double* params, const int32_t* seg, int64_t n,
+                          const fstat_refine_options* opt, double* params_out, double* F_out, int32_t* evals_out,
+                          void* hip_stream) {
+  if (!p || !params || n <= 0 || !opt || !params_out || !F_out) return FSTAT_EINVAL;
+  if (n > (int64_t)INT32_MAX) return FSTAT_EUNSUPPORTED;
+  for (int d = 0; d < 4; ++d)
+    if (!(opt->scale[d] > 0.0) || !std::isfinite(opt->scale[d])) return FSTAT_EINVAL;
+  if (!(opt->tol > 0.0) || opt->max_evals < 5 || opt->max_evals > 100000 || (opt->exact != 0 && opt->exact != 1))
+    return FSTAT_EINVAL;
+  DeviceGuard guard(p->device);
+  if (!guard.ok) return FSTAT_EDEVICE;
+  return from_hip(fsk::nelder_mead(p->d_segs, (int)p->segs.size(), seg, params, n, opt->scale, opt->tol,
+                                   opt->max_evals, opt->exact, params_out, F_out, evals_out,
+                                   (hipStream_t)hip_stream));
+}
+
+fstat_status fstat_threshold(double alpha, double n_cells, double* F0) {
+  if (!F0 || !(alpha > 0.0 && alpha < 1.0) || !(n_cells >= 1.0) || !std::isfinite(n_cells)) return FSTAT_EINVAL;
+  // per-cell false-alarm probability from Eq. (FP): P_F = 1 - (1 - alpha)^(1/N_c)
+  const double pf = -std::expm1(std::log1p(-alpha) / n_cells);
+  if (!(pf > 0.0) || !(pf < 1.0)) return FSTAT_EINVAL;
+  // invert Eq. (PF), P_F(F0) = (1 + F0) e^{-F0}, decreasing on F0 >= 0:
+  // solve h(F) = F - log(1 + F) + log P_F = 0 by bisection
+  const double lp = std::log(pf);
+  double lo = 0.0, hi = 1.0;
+  while (hi - std::log1p(hi) + lp < 0.0) hi *= 2.0;
+  for (int it = 0; it < 200; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (mid - std::log1p(mid) + lp < 0.0) lo = mid;
+    else hi = mid;
+  }
+  *F0 = 0.5 * (lo + hi);
+  return FSTAT_OK;
+}
+
 fstat_status fstat_amplitudes(fstat_plan_t p, const double* params, const int32_t* seg, int64_t n,
                               const double* state, double* out, void* hip_stream) {
   if (!p || !params || n <= 0 || !state || !out) return FSTAT_EINVAL;

@@ -115,4 +115,10 @@ hipError_t grad_adjoint(const SegDev* d_segs, int nseg, const int32_t* d_seg, co
                         const double* d_state, const double* d_gF, double* d_dp, hipStream_t st);
 hipError_t amplitudes(const SegDev* d_segs, int nseg, const int32_t* d_seg, const double* d_params, int64_t n,
                       const double* d_state, double* d_out, hipStream_t st);
+// search.hip
+hipError_t eval_exact(const SegDev* d_segs, int nseg, const int32_t* d_seg, const double* d_params, int64_t n,
+                      double* d_F, hipStream_t st);
+hipError_t nelder_mead(const SegDev* d_segs, int nseg, const int32_t* d_seg, const double* d_params, int64_t n,
+                       const double* scale, double tol, int max_evals, int exact, double* d_pout, double* d_F,
+                       int32_t* d_evals, hipStream_t st);
 }  // namespace fsk

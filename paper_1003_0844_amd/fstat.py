@@ -72,11 +72,17 @@ class _Out(ctypes.Structure):
                 ("n_crossings", ctypes.c_void_p), ("max_crossings", ctypes.c_int64)]
 
 
+class _RefineOptions(ctypes.Structure):
+    _fields_ = [("scale", ctypes.c_double * 4), ("tol", ctypes.c_double), ("max_evals", ctypes.c_int32),
+                ("exact", ctypes.c_int32)]
+
+
 NODE_DTYPE = np.dtype([("alpha", "<f8"), ("delta", "<f8"), ("fdot", "<f8"), ("seg", "<i4"), ("pad", "<i4")])
 CROSSING_DTYPE = np.dtype([("node", "<i8"), ("k", "<i8"), ("F", "<f8")])
 
 EXPORTS = ("fstat_plan", "fstat_grid", "fstat_graph_create", "fstat_graph_launch", "fstat_graph_destroy",
-           "fstat_eval", "fstat_adjoint", "fstat_amplitudes", "fstat_grad", "fstat_plan_info", "fstat_demod_series",
+           "fstat_eval", "fstat_eval_exact", "fstat_refine", "fstat_threshold", "fstat_adjoint", "fstat_amplitudes",
+           "fstat_grad", "fstat_plan_info", "fstat_demod_series",
            "fstat_profile",
            "fstat_profile_read", "fstat_plan_schedule", "fstat_destroy", "fstat_strerror")
 K_SKY, K_PASS1, K_PASS2, K_OTHER = 0, 1, 2, 3
@@ -102,6 +108,9 @@ def lib():
         L.fstat_adjoint.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp]
         L.fstat_grad.argtypes = [vp, vp, vp, i64, vp, vp, vp]
         L.fstat_amplitudes.argtypes = [vp, vp, vp, i64, vp, vp, vp]
+        L.fstat_eval_exact.argtypes = [vp, vp, vp, i64, vp, vp]
+        L.fstat_refine.argtypes = [vp, vp, vp, i64, P(_RefineOptions), vp, vp, vp, vp]
+        L.fstat_threshold.argtypes = [ctypes.c_double, ctypes.c_double, P(ctypes.c_double)]
         L.fstat_plan_info.argtypes = [vp, i32, P(i64), P(i64), P(ctypes.c_double), P(i32), P(i32)]
         L.fstat_demod_series.argtypes = [vp, vp, vp, vp]
         L.fstat_profile.argtypes = [vp, i32]
@@ -112,6 +121,7 @@ def lib():
         L.fstat_strerror.restype = ctypes.c_char_p
         L.fstat_destroy.restype = None
         for name in ("fstat_plan", "fstat_grid", "fstat_graph_create", "fstat_graph_launch", "fstat_amplitudes",
+                     "fstat_eval_exact", "fstat_refine", "fstat_threshold",
                      "fstat_eval", "fstat_adjoint", "fstat_grad", "fstat_plan_info",
                      "fstat_demod_series", "fstat_profile", "fstat_profile_read", "fstat_plan_schedule"):
             getattr(L, name).restype = i32
@@ -172,6 +182,14 @@ class SegmentSpec:
     f_ref: float = 435.1875
     sigma2: float = 1.0
     nfft: int = 0
+
+
+def threshold(alpha: float, n_cells: float) -> float:
+    """F0 with false-alarm probability alpha over n_cells independent cells
+    (fstat_threshold: Eqs. PF, FP)."""
+    F0 = ctypes.c_double()
+    _check(lib().fstat_threshold(float(alpha), float(n_cells), ctypes.byref(F0)), "fstat_threshold")
+    return F0.value
 
 
 def nodes_array(alpha, delta, fdot, seg=0) -> np.ndarray:
@@ -385,6 +403,29 @@ class Plan:
         _check(lib().fstat_adjoint(self._h, _ptr(params), _ptr(seg), n, _ptr(state.contiguous()), _ptr(gF),
                                    _ptr(dp), _stream_ptr(self.device)), "fstat_adjoint")
         return dp
+
+    def eval_exact(self, params: torch.Tensor, seg: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """F without resampling (direct sums on the detector samples), [n]."""
+        params, seg = self._params(params, seg)
+        F = torch.empty(params.shape[0], dtype=torch.float64, device=self._dev())
+        _check(lib().fstat_eval_exact(self._h, _ptr(params), _ptr(seg), params.shape[0], _ptr(F),
+                                      _stream_ptr(self.device)), "fstat_eval_exact")
+        return F
+
+    def refine(self, params: torch.Tensor, scale, tol: float = 1e-3, max_evals: int = 400, exact: bool = True,
+               seg: Optional[torch.Tensor] = None):
+        """Nelder-Mead fine search from each row of params: (best params [n, 4],
+        F [n], evaluations used [n])."""
+        params, seg = self._params(params, seg)
+        n = params.shape[0]
+        pout = torch.empty_like(params)
+        F = torch.empty(n, dtype=torch.float64, device=self._dev())
+        ev = torch.empty(n, dtype=torch.int32, device=self._dev())
+        o = _RefineOptions((ctypes.c_double * 4)(*[float(v) for v in scale]), float(tol), int(max_evals),
+                           1 if exact else 0)
+        _check(lib().fstat_refine(self._h, _ptr(params), _ptr(seg), n, ctypes.byref(o), _ptr(pout), _ptr(F),
+                                  _ptr(ev), _stream_ptr(self.device)), "fstat_refine")
+        return pout, F, ev
 
     def amplitudes(self, params: torch.Tensor, seg: Optional[torch.Tensor] = None) -> torch.Tensor:
         """[n, 8]: amplitudes A1..A4, h0, cos(iota), psi, phi0 at the candidates

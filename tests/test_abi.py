@@ -84,6 +84,12 @@ def test_calls_on_null_plan_are_rejected():
     assert L.fstat_grad(None, None, None, 1, None, None, None) == fstat.EINVAL
     assert L.fstat_adjoint(None, None, None, 1, None, None, None, None) == fstat.EINVAL
     assert L.fstat_plan_info(None, 0, None, None, None, None, None) == fstat.EINVAL
+    assert L.fstat_eval_exact(None, None, None, 1, None, None) == fstat.EINVAL
+    assert L.fstat_refine(None, None, None, 1, None, None, None, None, None) == fstat.EINVAL
+    assert L.fstat_amplitudes(None, None, None, 1, None, None, None) == fstat.EINVAL
+    assert L.fstat_graph_create(None, None, 1, None, None) == fstat.EINVAL
+    assert L.fstat_graph_launch(None, None) == fstat.EINVAL
+    L.fstat_graph_destroy(None)
     L.fstat_destroy(None)
 
 
@@ -93,3 +99,5 @@ def test_node_record_layout_matches_header():
     assert fstat.CROSSING_DTYPE.itemsize == 24
     assert ctypes.sizeof(fstat._Segment) == 72
     assert ctypes.sizeof(fstat._Out) == 80
+    # fstat_refine_options: 4 + 1 doubles, 2 int32
+    assert ctypes.sizeof(fstat._RefineOptions) == 48

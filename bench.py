@@ -55,10 +55,13 @@ def counters_run(args):
     from paper_1003_0844_amd import fstat
     w, x, nodes = workload()
     sub = nodes[:64]
-    plan = fstat.Plan([fstat.SegmentSpec(x=x, dt=w.dt, n_days=w.days, nfft=w.nfft)], fstat.default_detector(),
+    ib = bool(args.interbin)
+    nfft = (w.nfft // 2) if ib else w.nfft
+    half = nfft // 2
+    plan = fstat.Plan([fstat.SegmentSpec(x=x, dt=w.dt, n_days=w.days, nfft=nfft)], fstat.default_detector(),
                       fstat.Ephemeris(), interp=fstat.LINEAR_UP2, prec=fstat.FP32, max_batch=args.max_batch)
-    F = torch.empty((len(sub), w.nfft // 2), dtype=torch.float32, device="cuda")
-    plan.grid_map(sub, 0, w.nfft // 2, F)
+    F = torch.empty((len(sub), (2 if ib else 1) * half), dtype=torch.float32, device="cuda")
+    plan.grid_map(sub, 0, half, F, interbin=ib)
     torch.cuda.synchronize()
     src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
@@ -70,7 +73,8 @@ def counters_run(args):
     ev[1].record()
     torch.cuda.synchronize()
     ms = ev[0].elapsed_time(ev[1])
-    print(json.dumps({"counters_run": "done", "grid_nodes": len(sub), "copy_bytes_each_way": 1 << 30,
+    print(json.dumps({"counters_run": "done", "grid_nodes": len(sub), "nfft": nfft, "interbin": ib,
+                      "schedule": plan.schedule(), "copy_bytes_each_way": 1 << 30,
                       "copy_ms": round(ms, 4), "copy_GBps_read_plus_write": round(2 * (1 << 30) / ms / 1e6, 1)}),
           flush=True)
 

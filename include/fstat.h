@@ -96,7 +96,8 @@ typedef struct {
   double dt;                /* sampling interval, s */
   int32_t n_sidereal_days;  /* n dt / sidereal_day_s, >= 1 */
   double t0;                /* ephemeris time of the first sample, s */
-  const uint8_t *mask;      /* host [n] or NULL: 0 marks a gap (sample ignored) */
+  const uint8_t *mask;      /* host [n] or NULL: 0 marks a gap (sample ignored); at least
+                               one sample must be kept (FSTAT_EINVAL otherwise) */
   double f_ref_hz;          /* lower band edge */
   double sigma2;            /* noise variance per sample; <= 0: estimated from the
                                data outside gaps (unbiased sample variance) */

@@ -193,6 +193,11 @@ fstat_status validate_segment(const fstat_segment& s, const fstat_ephemeris& eph
   if (!is_pow2(nfft) || nfft < s.n || nfft < (1 << 10) || nfft > (1 << 22)) return FSTAT_EUNSUPPORTED;
   for (int64_t i = 0; i < s.n; ++i)
     if (!std::isfinite(s.x[i])) return FSTAT_EINVAL;
+  if (s.mask) {  // a segment made only of gaps has no data (A = B = 0)
+    int64_t kept = 0;
+    for (int64_t i = 0; i < s.n && kept == 0; ++i) kept += s.mask[i] != 0;
+    if (kept == 0) return FSTAT_EINVAL;
+  }
   (void)prec;
   return FSTAT_OK;
 }

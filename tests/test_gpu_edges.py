@@ -1,0 +1,118 @@
+"""Edge cases of the grid path: the largest and smallest supported FFT
+lengths, sky positions at the poles and at alpha = 0 / 2 pi, zero spindown,
+single-bin ranges, and the argument checks that need a plan."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import method
+from paper_1003_0844_amd import fstat, synth
+from tests.common import DET, EPH, small_segment
+from tests.gpu_common import PREC_TOL, banner, f_error, make_plan, oracle_map
+
+pytestmark = pytest.mark.gpu
+
+
+def test_largest_fft_length():
+    # N = 2^21 samples over one sidereal day, nfft = 2^22 (the largest
+    # supported): split R = 1024, C = 4096 in both precisions
+    n = 1 << 21
+    dt = synth.SIDEREAL_DAY / n
+    seg = small_segment(days=1, dt=dt, seed=51, nfft=1 << 22)
+    banner("largest nfft", seg.n, seg.fft_len)
+    nodes = fstat.nodes_array([0.7], [-0.4], [-5e-10])
+    half = seg.fft_len // 2
+    k = np.unique(np.r_[np.random.default_rng(1).integers(0, half, 48), 0, half - 1])
+    ref = method.fstat_bins(seg, -5e-10, 0.7, -0.4, DET, EPH, method.LINEAR_UP2, k=k)
+    for prec in (fstat.FP32, fstat.FP64):
+        plan = make_plan([seg], method.LINEAR_UP2, prec)
+        assert plan.schedule()["R"] * plan.schedule()["C"] == seg.fft_len
+        F = plan.grid_map(nodes, 0, half)[0].cpu().numpy()
+        assert f_error(F[k], ref) < PREC_TOL[prec], prec
+        del plan
+        torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("mode", [method.NEAREST, method.LINEAR_UP2, method.CUBIC_UP2])
+def test_smallest_fft_length(mode):
+    # N = 512, nfft = 2^10 (the smallest supported): split R = 16, C = 64
+    n = 512
+    dt = synth.SIDEREAL_DAY / n
+    seg = small_segment(days=1, dt=dt, seed=52, nfft=1 << 10)
+    banner("smallest nfft", mode)
+    al, de = synth.sky_uniform(synth.rng(52), 3)
+    nodes = fstat.nodes_array(al, de, [0.0, -1e-9, -3e-10])
+    half = seg.fft_len // 2
+    for prec in (fstat.FP32, fstat.FP64):
+        F = make_plan([seg], mode, prec).grid_map(nodes, 0, half).cpu().numpy()
+        for i, nd in enumerate(nodes):
+            ref = oracle_map(seg, nd["fdot"], nd["alpha"], nd["delta"], mode, np.arange(half))
+            assert f_error(F[i], ref) < PREC_TOL[prec], (prec, i)
+
+
+@pytest.mark.parametrize("prec", [fstat.FP32, fstat.FP64])
+def test_poles_wraparound_and_zero_spindown(prec):
+    seg = small_segment(days=1, dt=13.0, seed=53, nfft=16384)
+    banner("poles", prec)
+    alpha = [0.3, 2.0, 0.0, 2 * math.pi - 1e-9, 1.0]
+    delta = [math.pi / 2, -math.pi / 2, 0.2, 0.2, 0.0]
+    fdot = [0.0, 0.0, -1e-9, -1e-9, 0.0]
+    nodes = fstat.nodes_array(alpha, delta, fdot)
+    half = seg.fft_len // 2
+    F = make_plan([seg], method.CUBIC_UP2, prec).grid_map(nodes, 0, half).cpu().numpy()
+    for i, nd in enumerate(nodes):
+        ref = oracle_map(seg, nd["fdot"], nd["alpha"], nd["delta"], method.CUBIC_UP2, np.arange(half))
+        assert f_error(F[i], ref) < PREC_TOL[prec], i
+    # alpha = 0 and alpha = 2 pi - 1e-9 are the same sky position up to 1e-9 rad
+    assert f_error(F[2], F[3]) < 1e-4
+
+
+def test_single_bin_ranges():
+    seg = small_segment(days=1, dt=13.0, seed=54, nfft=16384)
+    banner("single bins")
+    plan = make_plan([seg], method.LINEAR_UP2, fstat.FP32)
+    nodes = fstat.nodes_array([0.5, 1.5], [0.1, -0.7], [0.0, -2e-10])
+    half = seg.fft_len // 2
+    full = plan.grid_map(nodes, 0, half)
+    for lo in (0, 1, half - 1):
+        part = plan.grid_map(nodes, lo, lo + 1)
+        assert torch.equal(part[:, 0], full[:, lo])
+    Fmax, kmax = plan.grid_max(nodes, half - 1, half)
+    assert torch.equal(Fmax, full[:, half - 1]) and bool((kmax == half - 1).all())
+
+
+def test_argument_checks_with_a_plan():
+    seg = small_segment(days=1, dt=13.0, seed=55, nfft=16384)
+    banner("argument checks")
+    plan = make_plan([seg], method.LINEAR_UP2, fstat.FP32)
+    half = seg.fft_len // 2
+    nodes = fstat.nodes_array([0.5], [0.1], [0.0])
+
+    def status(fn):
+        with pytest.raises(fstat.FStatError) as e:
+            fn()
+        return e.value.status
+
+    assert status(lambda: plan.grid_map(nodes[:0], 0, half)) == fstat.EINVAL
+    assert status(lambda: plan.grid_map(nodes, 0, half + 1)) == fstat.EINVAL
+    assert status(lambda: plan.grid_map(nodes, 5, 5)) == fstat.EINVAL
+    bad = nodes.copy()
+    bad["seg"] = 1
+    assert status(lambda: plan.grid_map(bad, 0, half)) == fstat.EINVAL
+    bad = nodes.copy()
+    bad["delta"] = float("nan")
+    assert status(lambda: plan.grid_map(bad, 0, half)) == fstat.EINVAL
+    out = fstat._Out(mode=fstat.OUT_MAP, interbin=2, k_lo=0, k_hi=half, F=1)
+    assert status(lambda: plan._grid(nodes, out)) == fstat.EINVAL
+    # plan-time checks: FFT length, whole sidereal days, a segment of gaps only
+    x = seg.x
+    det, eph = fstat.detector_spec(DET), fstat.ephemeris_spec(EPH)
+    mk = lambda **kw: fstat.Plan([fstat.SegmentSpec(**{**dict(x=x, dt=seg.dt, n_days=1, f_ref=seg.f_ref), **kw})],
+                                 det, eph)
+    assert status(lambda: mk(nfft=12000)) == fstat.EUNSUPPORTED
+    assert status(lambda: mk(nfft=4096)) == fstat.EUNSUPPORTED
+    assert status(lambda: mk(n_days=2)) == fstat.ENOTINTDAYS
+    assert status(lambda: mk(mask=np.zeros(len(x), dtype=np.uint8))) == fstat.EINVAL
+    assert status(lambda: mk(x=np.r_[x[:-1], np.inf])) == fstat.EINVAL

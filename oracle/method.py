@@ -271,15 +271,29 @@ def combine(Sa, Sb, A, B, C, sigma2):
     return num / (sigma2 * (A * B - C * C))
 
 
-def fstat_bins(seg: Segment, fdot, alpha, delta, det, eph, mode, k=None, dft="direct"):
+def shift_bins(z, nfft, bin_offset):
+    """z_j e^{-2 pi i off j / nfft}: its DFT at bin k is the transform of z at
+    the frequency (k + off) / (nfft dt), so a line of Fourier bins can start a
+    fraction of a bin off zero (the frequency lines of the lattice grid of
+    Sec. IV, Eq. avec)."""
+    if bin_offset == 0.0:
+        return z
+    j = np.arange(len(z), dtype=np.float64)
+    cyc = float(bin_offset) * j / nfft
+    return z * np.exp(-2j * math.pi * (cyc - np.round(cyc)))
+
+
+def fstat_bins(seg: Segment, fdot, alpha, delta, det, eph, mode, k=None, dft="direct", bin_offset=0.0):
     """F on Fourier bins k (default: all of [0, nfft/2)) by the resampling
-    method.  dft='direct' sums the DFT term by term; dft='fft' uses numpy's
-    FP64 FFT of the zero-padded series for the same sums."""
+    method, at the frequencies (k + bin_offset) / (nfft dt).  dft='direct' sums
+    the DFT term by term; dft='fft' uses numpy's FP64 FFT of the zero-padded
+    series for the same sums."""
     nfft = seg.fft_len
     if k is None:
         k = np.arange(nfft // 2, dtype=np.int64)
     k = np.asarray(k, dtype=np.int64)
     za, zb = demodulated(seg, fdot, alpha, delta, det, eph, mode)
+    za, zb = shift_bins(za, nfft, bin_offset), shift_bins(zb, nfft, bin_offset)
     if dft == "direct":
         Sa, Sb = sums.dft_bins(za, nfft, k), sums.dft_bins(zb, nfft, k)
     elif dft == "fft":
@@ -296,10 +310,12 @@ def interbin(S_k, S_k1):
     return (np.asarray(S_k1) - np.asarray(S_k)) / math.sqrt(2.0)
 
 
-def fstat_bins_interbinned(seg: Segment, fdot, alpha, delta, det, eph, mode, k=None, dft="direct"):
+def fstat_bins_interbinned(seg: Segment, fdot, alpha, delta, det, eph, mode, k=None, dft="direct",
+                           bin_offset=0.0):
     """F at the Fourier bins k and at the half bins k + 1/2: Eq. (intbin)
     applied to S_a and S_b, then the F combination.  Needs k + 1 <= nfft/2.
-    Returns (F at k, F at k + 1/2)."""
+    Bins start bin_offset off zero as in fstat_bins.  Returns (F at k, F at
+    k + 1/2)."""
     nfft = seg.fft_len
     if k is None:
         k = np.arange(nfft // 2, dtype=np.int64)
@@ -308,6 +324,7 @@ def fstat_bins_interbinned(seg: Segment, fdot, alpha, delta, det, eph, mode, k=N
         raise ValueError("bins k and k + 1 must lie in [0, nfft/2]")
     kk = np.union1d(k, k + 1)
     za, zb = demodulated(seg, fdot, alpha, delta, det, eph, mode)
+    za, zb = shift_bins(za, nfft, bin_offset), shift_bins(zb, nfft, bin_offset)
     if dft == "direct":
         Sa, Sb = sums.dft_bins(za, nfft, kk), sums.dft_bins(zb, nfft, kk)
     elif dft == "fft":

@@ -113,3 +113,69 @@ def test_wrong_derivative_of_delay_is_caught(monkeypatch):
     monkeypatch.setattr(method, "_roemer_partials", bad)
     _fails(tg.test_roemer_partials_match_finite_differences)
     _fails(tf.test_gradient_matches_central_differences, method.CUBIC_UP2, 1e-6)
+
+
+# ------------------------------------------------------ lattice grid (Sec. IV)
+from oracle import lattice as lat_oracle  # noqa: E402
+from tests import test_oracle_lattice as tl  # noqa: E402
+
+
+def test_uncentred_fisher_matrix_is_caught(monkeypatch):
+    def bad(m, weights=None):
+        m = np.asarray(m, dtype=np.float64)
+        w = np.ones(m.shape[1]) if weights is None else np.asarray(weights, dtype=np.float64)
+        w = w / w.sum()
+        return (m * w) @ m.T                       # <m_k m_l> without -<m_k><m_l>
+    monkeypatch.setattr(lat_oracle, "reduced_fisher", bad)
+    _fails(tl.test_reduced_fisher_of_the_2d_example)
+
+
+def test_wrong_sign_in_the_a4star_generator_is_caught(monkeypatch):
+    orig = lat_oracle.generator_a4star
+
+    def bad(R):
+        G = orig(R).copy()
+        G[3, 1] = -G[3, 1]
+        return G
+    monkeypatch.setattr(lat_oracle, "generator_a4star", bad)
+    _fails(tl.test_a2star_and_a4star_generators)
+
+
+def test_printed_nu_iteration_is_caught(monkeypatch):
+    # nu = R / (R_1 sin phi) from the lattice shrunk along l: not the covering
+    # the worked example prints
+    def bad(verts, l, mu, R):
+        lh = l / np.linalg.norm(l)
+        c = verts @ lh
+        p = np.sqrt(np.maximum(np.einsum("ij,ij->i", verts, verts) - c * c, 0.0))
+        img = np.sqrt(mu * mu * c * c + p * p)
+        i = int(np.argmax(np.arccos(np.clip(np.abs(c) / np.linalg.norm(verts, axis=1), 0, 1))))
+        return R / (img.max() * (p[i] / np.linalg.norm(verts[i])))
+    monkeypatch.setattr(lat_oracle, "expansion_nu", bad)
+    _fails(tl.test_the_2d_worked_example)
+
+
+def test_sky_parameters_swapped_are_caught(monkeypatch):
+    orig = lat_oracle.sky_direction
+
+    def bad(a1, a2, omega_s, hemisphere, obliquity):
+        return orig(a2, a1, omega_s, hemisphere, obliquity)
+    monkeypatch.setattr(lat_oracle, "sky_direction", bad)
+    _fails(tl.test_sky_directions_invert_the_sky_parameters)
+
+
+def test_dropped_diurnal_term_of_mu1_is_caught(monkeypatch):
+    orig = lat_oracle.linear_model_functions
+
+    def bad(t, T0, det, eph):
+        m = orig(t, T0, det, eph)
+        xes, yes = model.earth_center(T0 + np.asarray(t), eph)
+        m[2] = yes / model.C_LIGHT
+        return m
+    monkeypatch.setattr(lat_oracle, "linear_model_functions", bad)
+    _fails(tl.test_linear_model_drops_only_the_ecliptic_normal_motion)
+
+
+def test_unshifted_bins_are_caught(monkeypatch):
+    monkeypatch.setattr(method, "shift_bins", lambda z, nfft, off: z)
+    _fails(tl.test_offset_bins_are_the_continuous_transform)

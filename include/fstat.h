@@ -133,13 +133,18 @@ typedef struct fstat_plan_s *fstat_plan_t;
 fstat_status fstat_plan(const fstat_segment *segs, int32_t nseg, const fstat_detector *det,
                         const fstat_ephemeris *eph, const fstat_options *opt, fstat_plan_t *out);
 
-/* A grid node: sky position, spindown (Hz/s), segment index. */
+/* A grid node: sky position, spindown (Hz/s), segment index, and the offset of
+ * its line of Fourier bins.  Output bin k of a node is the band-relative
+ * frequency (k + bin_offset) / (nfft dt): the nodes of a lattice grid lie on
+ * lines parallel to the frequency axis spaced by one Fourier bin, each line
+ * shifted by a fraction of a bin (Sec. IV, Eq. avec).  0 gives the plain
+ * Fourier frequencies; |bin_offset| < 1 (FSTAT_EINVAL otherwise). */
 typedef struct {
-  double alpha;   /* right ascension, rad */
-  double delta;   /* declination, rad */
-  double fdot;    /* first spindown, Hz/s */
-  int32_t seg;    /* segment of the plan */
-  int32_t pad;
+  double alpha;       /* right ascension, rad */
+  double delta;       /* declination, rad */
+  double fdot;        /* first spindown, Hz/s */
+  int32_t seg;        /* segment of the plan */
+  float bin_offset;   /* in Fourier bins */
 } fstat_node;
 
 /* A threshold crossing (output mode FSTAT_OUT_CROSSINGS). */
@@ -271,6 +276,74 @@ fstat_status fstat_refine(fstat_plan_t p, const double *params, const int32_t *s
  * of false alarms is N_c P_F(F0) (Eq. NF). */
 fstat_status fstat_threshold(double alpha, double n_cells, double *F0);
 
+/* ---- The lattice grid of Sec. IV (host computations, no device) --------------
+ * Phase parameters of the linear model with one spindown (Sec. III B, Eqs.
+ * philin, albe, siglin): xi = (omega_0 [rad/s], omega_1 [rad/s^2], alpha_1,
+ * alpha_2 [rad/s]) with the known functions m = (t, t^2/2, mu_1(t), mu_2(t)),
+ * mu_1 = (R^y_ES + R^y_E cos eps)/c, mu_2 = (R^x_ES + R^x_E)/c, t the segment
+ * time.  alpha_1 = omega (n_y), alpha_2 = omega (n_x) in the ecliptic frame. */
+
+/* Reduced Fisher matrix of Eq. (redFm-def), G_kl = <m_k m_l> - <m_k><m_l>, the
+ * average over the kept samples t_j = j dt of one segment (its x is not read).
+ *   gamma: host [4][4] row-major, written.
+ * FSTAT_EINVAL: a NULL pointer, n < 2, dt <= 0, fewer than 2 kept samples. */
+fstat_status fstat_lattice_fisher(const fstat_segment *seg, const fstat_detector *det, const fstat_ephemeris *eph,
+                                  double gamma[16]);
+
+/* A covering lattice of the correlation hyperellipsoid G(tau, tau) = 1 - C0
+ * (Eq. hype): A4* (Eq. gen, thickness 1.7655) with covering radius
+ * R = sqrt(1 - C0) in whitened coordinates, shrunk by mu along a lattice vector
+ * l and expanded by nu across it so that l maps onto a0 = (dp0, 0, 0, 0)
+ * (Eqs. avec, opt), then turned about a0 so that a second basis vector has no
+ * sky components (Eqs. constraint2, opt2).  Every parameter point lies within
+ * correlation C0 (in the linear model) of a lattice point. */
+typedef struct {
+  double basis[16];    /* rows a0..a3 (row-major [4][4], xi coordinates): a0 = (dp0, 0, 0, 0);
+                          a1 = (a10, a11, 0, 0); a2, a3 the sky vectors, their sky projections
+                          Lagrange-Gauss reduced, |omega_1 part| <= |a11|/2, |omega_0 part| <= dp0/2 */
+  double gamma[16];    /* the reduced Fisher matrix it was built for */
+  double dp0;          /* angular frequency spacing of the Fourier bins, 2 pi / (nfft dt) */
+  double c0;           /* minimal correlation C0 */
+  double R;            /* sqrt(1 - C0) */
+  double mu, nu;       /* shrink along l, expansion across it */
+  double theta;        /* thickness 1.7655 / (mu nu^3) */
+  double margin_w1;    /* half-width of a covering ellipsoid's shadow on the omega_1 axis */
+  double margin_sky;   /* its largest half-width in the (alpha_1, alpha_2) plane */
+} fstat_lattice;
+
+/*   gamma: host [4][4] symmetric positive definite; dp0 > 0; 0 < c0 < 1.
+ * FSTAT_EINVAL: arguments out of range, gamma not positive definite or too
+ * ill-conditioned for the constraints to hold to 1e-9. */
+fstat_status fstat_lattice_build(const double gamma[16], double dp0, double c0, fstat_lattice *out);
+
+/* A sky region and spindown range to cover. */
+typedef struct {
+  double f_sky_hz;      /* frequency of the sky mapping, omega_s = 2 pi f_sky (the top of the band:
+                           the finest sky resolution the band needs) */
+  double fdot_lo, fdot_hi;            /* spindown range, Hz/s */
+  double sky_c1, sky_c2, sky_radius;  /* a disk in the (alpha_1, alpha_2) plane, rad/s;
+                                         sky_radius <= 0: the whole sky disk |alpha| <= omega_s */
+  int32_t hemisphere;   /* +1 / -1: ecliptic north / south only; 0: both */
+  int32_t seg;          /* written into every node */
+} fstat_lattice_region;
+
+/* The grid nodes of a lattice over a region: every lattice point whose covering
+ * ellipsoid reaches the region (the ranges widened by the margins), one node per
+ * (sky point, spindown); the node's Fourier bins k are the lattice points
+ * k a0 + (its omega_0), so its bin_offset is frac(omega_0 / dp0) (a float32; a
+ * value that rounds to 1 is 0).  A sky point inside the disk gives both
+ * directions n_z = +-sqrt(1 - n_x^2 - n_y^2) (the linear model does not tell
+ * them apart) unless hemisphere selects one; one outside it is put on the
+ * ecliptic (n scaled to unit length).  Order: sky points (k2 outer, k3 inner),
+ * then direction, then k1.
+ *   nodes: host [capacity] or NULL when capacity = 0; coef: host [capacity][3]
+ *   lattice coefficients (k1, k2, k3) of a1, a2, a3, or NULL.
+ *   *count receives the number of nodes of the region; min(count, capacity)
+ *   are written.  The obliquity is the ephemeris's. */
+fstat_status fstat_lattice_nodes(const fstat_lattice *lat, const fstat_lattice_region *reg,
+                                 const fstat_ephemeris *eph, fstat_node *nodes, int32_t *coef, int64_t capacity,
+                                 int64_t *count);
+
 /* Convenience: F and (if dF != NULL) dF/d(f, fdot, alpha, delta), device [n] and [n][4]. */
 fstat_status fstat_grad(fstat_plan_t p, const double *params, const int32_t *seg, int64_t n, double *F,
                         double *dF, void *hip_stream);
@@ -286,7 +359,8 @@ fstat_status fstat_plan_schedule(fstat_plan_t p, int32_t seg, int32_t *R, int32_
 
 /* Diagnostic: the demodulated, resampled, a/b-weighted series z_a, z_b of one
  * node (the input of the FFTs, natural order), as FP64 device [n][4] =
- * (Re z_a, Im z_a, Re z_b, Im z_b), computed in the plan's precision. */
+ * (Re z_a, Im z_a, Re z_b, Im z_b), computed in the plan's precision, with the
+ * node's bin offset applied as the factor e^{-2 pi i bin_offset j / nfft}. */
 fstat_status fstat_demod_series(fstat_plan_t p, const fstat_node *node, double *out, void *hip_stream);
 
 /* Kernel timing (a tracing aid, off by default).  While enabled, every kernel

@@ -27,11 +27,13 @@ L-white  Any M with M^T G M = 1 maps the hyperellipsoid of Eq. (hype) to a
          M = D U diag(lambda)^-1/2.  It differs from Eq. (mmatr) by a rotation,
          which the choice of O2 absorbs.
 L-nu     The expansion factor nu.  The paper defines it by the covering radius
-         staying R and gives an iteration whose printed form does not converge
-         to a covering; its worked example has nu = sqrt(108 - pi^2)/9.  That
-         value is exactly the largest nu for which the images of the deep holes
-         of the starting lattice (the vertices of its Voronoi cell) stay within
-         distance R of the origin:
+         staying R and gives an iteration nu_i = R / (R_i sin phi_i) whose
+         results disagree with its worked numbers (followed literally it gives
+         nu = 1.641 on the two-dimensional example, and in four dimensions a
+         fixed point whose covering radius exceeds R); the example prints
+         nu = sqrt(108 - pi^2)/9.  That value is exactly the largest nu for
+         which the images of the deep holes of the starting lattice (the
+         vertices of its Voronoi cell) stay within distance R of the origin:
              nu^2 = min over vertices v of (R^2 - mu^2 (v.l^)^2) / (|v|^2 - (v.l^)^2).
          The image of a Voronoi cell under a linear map is a fundamental domain
          of the image lattice and contains the origin's nearest-point region up
@@ -423,7 +425,8 @@ def reduce_basis(B):
 def margins(G, R):
     """Reading L-margin: half-widths of the covering ellipsoid's shadow on the
     omega_1 axis and in the sky plane."""
-    Gi = np.linalg.inv(G)
+    D = np.diag(1.0 / np.sqrt(np.diag(G)))
+    Gi = D @ np.linalg.inv(D @ G @ D) @ D      # G^-1, inverted in the scaled form
     return R * math.sqrt(Gi[1, 1]), R * math.sqrt(float(np.linalg.eigvalsh(Gi[2:, 2:]).max()))
 
 

@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libfstat.so")
-SOURCES = ["api.hip", "sky.hip", "grid.hip", "prep.hip", "grad.hip", "search.hip"]
+SOURCES = ["api.hip", "sky.hip", "grid.hip", "prep.hip", "grad.hip", "search.hip", "lattice.cpp"]
 ARCH = os.environ.get("FSTAT_OFFLOAD_ARCH", "gfx950")
 
 
@@ -38,8 +38,12 @@ def build_library(verbose: bool = False) -> str:
     hipcc = _hipcc()
 
     def compile_one(src):
-        obj = os.path.join(HERE, "_objs", src.replace(".hip", ".o"))
-        cmd = [hipcc, *common_flags(), "-c", os.path.join(CSRC, src), "-o", obj]
+        obj = os.path.join(HERE, "_objs", os.path.splitext(src)[0] + ".o")
+        if src.endswith(".cpp"):   # host-only C++
+            cmd = [hipcc, "-x", "c++", "-O3", "-std=c++17", "-fPIC", "-I" + os.path.join(ROOT, "include"),
+                   "-I" + CSRC, "-c", os.path.join(CSRC, src), "-o", obj]
+        else:
+            cmd = [hipcc, *common_flags(), "-c", os.path.join(CSRC, src), "-o", obj]
         r = subprocess.run(cmd, capture_output=True, text=True)
         if r.returncode != 0:
             raise RuntimeError("hipcc failed for %s:\n%s" % (src, r.stderr[-6000:]))

@@ -424,7 +424,7 @@ void schedule_grid(const fstat_plan_s* p, const fstat_node* nodes, int64_t n_nod
         sky_ad.push_back(nd.delta);
         ++b.nsky;
       }
-      ndev.push_back(NodeDev{nd.fdot, b.nsky - 1, (int32_t)order[i]});
+      ndev.push_back(NodeDev{nd.fdot, (double)nd.bin_offset / (double)d.nfft, b.nsky - 1, (int32_t)order[i]});
       ++b.nnode;
       ++i;
     }
@@ -638,7 +638,7 @@ fstat_status tune_segment(fstat_plan_s* p, int si) {
       nd.delta = -1.2 + 0.3 * s;
       nd.fdot = -1e-9 * f / (nfd - 1);
       nd.seg = si;
-      nd.pad = 0;
+      nd.bin_offset = 0.0f;
     }
   const int64_t kh = nfft / 2;
   void* scratch = nullptr;
@@ -832,7 +832,7 @@ fstat_status check_grid_args(const fstat_plan_s* p, const fstat_node* nodes, int
   for (int64_t i = 0; i < n_nodes; ++i) {
     const fstat_node& nd = nodes[i];
     if (nd.seg < 0 || nd.seg >= nseg || !std::isfinite(nd.alpha) || !std::isfinite(nd.delta) ||
-        !std::isfinite(nd.fdot))
+        !std::isfinite(nd.fdot) || !(std::fabs(nd.bin_offset) < 1.0f))
       return FSTAT_EINVAL;
     if (out->k_hi > p->segs[nd.seg].dev.nfft / 2) return FSTAT_EINVAL;
   }
@@ -1033,6 +1033,9 @@ fstat_status fstat_grad(fstat_plan_t p, const double* params, const int32_t* seg
 fstat_status fstat_demod_series(fstat_plan_t p, const fstat_node* node, double* out, void* hip_stream) {
   if (!p || !node || !out) return FSTAT_EINVAL;
   if (node->seg < 0 || node->seg >= (int32_t)p->segs.size()) return FSTAT_EINVAL;
+  if (!std::isfinite(node->alpha) || !std::isfinite(node->delta) || !std::isfinite(node->fdot) ||
+      !(std::fabs(node->bin_offset) < 1.0f))
+    return FSTAT_EINVAL;
   DeviceGuard guard(p->device);
   if (!guard.ok) return FSTAT_EDEVICE;
   hipStream_t st = (hipStream_t)hip_stream;
@@ -1059,7 +1062,8 @@ fstat_status fstat_demod_series(fstat_plan_t p, const fstat_node* node, double* 
   const int64_t qstride = (int64_t)d.R * d.Ceff;
   HIP_TRY(fsk::sky_setup(d_ad, 1, d, d_sky, st));
   HIP_TRY(fsk::sky_prep(p->prec, d, d_sky, 1, d_quads, qstride, d_abc, nblk, st));
-  return from_hip(fsk::demod_series(p->prec, d, d_sky, d_quads, qstride, node->fdot, out, st));
+  return from_hip(fsk::demod_series(p->prec, d, d_sky, d_quads, qstride, node->fdot,
+                                    (double)node->bin_offset / (double)d.nfft, out, st));
 }
 
 }  // extern "C"

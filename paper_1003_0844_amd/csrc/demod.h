@@ -26,10 +26,11 @@ __device__ __forceinline__ void sincos_turns(double x, double& s, double& c) {
 
 template <typename T>
 __device__ __forceinline__ Pair<T> demod_elem(const Quad<T>& q, double tb0, int64_t j, double dt,
-                                              double fdot) {
+                                              double fdot, double fshift) {
   const double dd = (double)q.dd;  // phi_m(t_j) - phi_m(0)
   const double t = (double)j * dt - dd;
-  double cyc = (double)q.p0 + fdot * (t * (0.5 * t + tb0 + dd));
+  // fshift j moves the transform's bins by a fraction of a bin (lattice lines)
+  double cyc = (double)q.p0 + fdot * (t * (0.5 * t + tb0 + dd)) + fshift * (double)j;
   cyc -= rint(cyc);
   T s, c;
   sincos_turns(cyc, s, c);

@@ -48,11 +48,12 @@ k_pass1(SegDev sg, const Quad<T>* __restrict__ quads, int64_t qstride, const Sky
   const Quad<T>* __restrict__ col = quads + (int64_t)node.sky * qstride + (int64_t)r * sg.Ceff;
   const double tb0 = skies[node.sky].tb0;
   const double fdot = node.fdot;
+  const double fshift = node.fshift;
   const int ceff = sg.Ceff;
   const int R = sg.R;
   const double dt = sg.dt;
   auto load = [&](int c, int) -> Pair<T> {
-    if (c < ceff) return demod_elem<T>(col[c], tb0, (int64_t)r + (int64_t)R * c, dt, fdot);
+    if (c < ceff) return demod_elem<T>(col[c], tb0, (int64_t)r + (int64_t)R * c, dt, fdot, fshift);
     return Pair<T>{{(T)0, (T)0}, {(T)0, (T)0}};
   };
   Pair<T>* __restrict__ dst = spill + (int64_t)nd * sg.nfft + (int64_t)r * C;

@@ -26,8 +26,9 @@ struct SkyCoef {
 // One node of a grid batch.
 struct NodeDev {
   double fdot;
-  int32_t sky;   // index into the sky batch
-  int32_t row;   // output row (the caller's node index)
+  double fshift;  // bin offset / nfft: cycles per sample added to the demodulation phase
+  int32_t sky;    // index into the sky batch
+  int32_t row;    // output row (the caller's node index)
 };
 
 // Everything about a segment that the kernels need.
@@ -86,7 +87,7 @@ hipError_t sky_prep(int prec, const SegDev& seg, const SkyConst* d_sky, int nsky
 hipError_t sky_finalize(const SegDev& seg, const double* d_abc_part, int nblk_abc, int nsky, SkyCoef* d_coef,
                         hipStream_t st);
 hipError_t demod_series(int prec, const SegDev& seg, const SkyConst* d_sky, const void* d_quads,
-                        int64_t quad_stride, double fdot, double* d_out, hipStream_t st);
+                        int64_t quad_stride, double fdot, double fshift, double* d_out, hipStream_t st);
 // grid.hip
 int pass2_b2(int prec, int R);
 hipError_t grid_pass1(int prec, int C, const SegDev& seg, const void* d_quads, int64_t quad_stride,

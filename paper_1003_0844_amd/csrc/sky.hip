@@ -177,11 +177,11 @@ k_sky_finalize(const double* __restrict__ part, int nblk, double sigma2, SkyCoef
 
 template <typename T>
 __global__ void k_demod_series(SegDev sg, const SkyConst* __restrict__ sky, const Quad<T>* __restrict__ q,
-                               double fdot, double* __restrict__ out) {
+                               double fdot, double fshift, double* __restrict__ out) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= sg.n) return;
   const int64_t r = j % sg.R, c = j / sg.R;
-  const Pair<T> z = demod_elem<T>(q[r * sg.Ceff + c], sky[0].tb0, j, sg.dt, fdot);
+  const Pair<T> z = demod_elem<T>(q[r * sg.Ceff + c], sky[0].tb0, j, sg.dt, fdot, fshift);
   out[4 * j] = (double)z.a.x;
   out[4 * j + 1] = (double)z.a.y;
   out[4 * j + 2] = (double)z.b.x;
@@ -230,14 +230,14 @@ hipError_t sky_finalize(const SegDev& seg, const double* d_part, int nblk, int n
 }
 
 hipError_t demod_series(int prec, const SegDev& seg, const SkyConst* d_sky, const void* d_quads, int64_t,
-                        double fdot, double* d_out, hipStream_t st) {
+                        double fdot, double fshift, double* d_out, hipStream_t st) {
   dim3 grid((unsigned)((seg.n + 255) / 256)), block(256);
   if (prec == 0)
     hipLaunchKernelGGL(k_demod_series<float>, grid, block, 0, st, seg, d_sky, (const Quad<float>*)d_quads, fdot,
-                       d_out);
+                       fshift, d_out);
   else
     hipLaunchKernelGGL(k_demod_series<double>, grid, block, 0, st, seg, d_sky, (const Quad<double>*)d_quads,
-                       fdot, d_out);
+                       fdot, fshift, d_out);
   return hipGetLastError();
 }
 

@@ -54,6 +54,18 @@ class _Ephemeris(ctypes.Structure):
                 ("sidereal_day_s", ctypes.c_double), ("gmst0_rad", ctypes.c_double)]
 
 
+class _Lattice(ctypes.Structure):
+    _fields_ = [("basis", ctypes.c_double * 16), ("gamma", ctypes.c_double * 16), ("dp0", ctypes.c_double),
+                ("c0", ctypes.c_double), ("R", ctypes.c_double), ("mu", ctypes.c_double), ("nu", ctypes.c_double),
+                ("theta", ctypes.c_double), ("margin_w1", ctypes.c_double), ("margin_sky", ctypes.c_double)]
+
+
+class _LatticeRegion(ctypes.Structure):
+    _fields_ = [("f_sky_hz", ctypes.c_double), ("fdot_lo", ctypes.c_double), ("fdot_hi", ctypes.c_double),
+                ("sky_c1", ctypes.c_double), ("sky_c2", ctypes.c_double), ("sky_radius", ctypes.c_double),
+                ("hemisphere", ctypes.c_int32), ("seg", ctypes.c_int32)]
+
+
 class _Segment(ctypes.Structure):
     _fields_ = [("x", ctypes.POINTER(ctypes.c_double)), ("n", ctypes.c_int64), ("dt", ctypes.c_double),
                 ("n_sidereal_days", ctypes.c_int32), ("t0", ctypes.c_double),
@@ -78,12 +90,13 @@ class _RefineOptions(ctypes.Structure):
                 ("exact", ctypes.c_int32)]
 
 
-NODE_DTYPE = np.dtype([("alpha", "<f8"), ("delta", "<f8"), ("fdot", "<f8"), ("seg", "<i4"), ("pad", "<i4")])
+NODE_DTYPE = np.dtype([("alpha", "<f8"), ("delta", "<f8"), ("fdot", "<f8"), ("seg", "<i4"), ("bin_offset", "<f4")])
 CROSSING_DTYPE = np.dtype([("node", "<i8"), ("k", "<i8"), ("F", "<f8")])
 
 EXPORTS = ("fstat_plan", "fstat_grid", "fstat_graph_create", "fstat_graph_launch", "fstat_graph_destroy",
            "fstat_eval", "fstat_eval_exact", "fstat_refine", "fstat_threshold", "fstat_adjoint", "fstat_amplitudes",
            "fstat_grad", "fstat_plan_info", "fstat_demod_series",
+           "fstat_lattice_fisher", "fstat_lattice_build", "fstat_lattice_nodes",
            "fstat_profile",
            "fstat_profile_read", "fstat_plan_schedule", "fstat_destroy", "fstat_strerror")
 K_SKY, K_PASS1, K_PASS2, K_OTHER = 0, 1, 2, 3
@@ -112,6 +125,9 @@ def lib():
         L.fstat_eval_exact.argtypes = [vp, vp, vp, i64, vp, vp]
         L.fstat_refine.argtypes = [vp, vp, vp, i64, P(_RefineOptions), vp, vp, vp, vp]
         L.fstat_threshold.argtypes = [ctypes.c_double, ctypes.c_double, P(ctypes.c_double)]
+        L.fstat_lattice_fisher.argtypes = [P(_Segment), P(_Detector), P(_Ephemeris), P(ctypes.c_double)]
+        L.fstat_lattice_build.argtypes = [P(ctypes.c_double), ctypes.c_double, ctypes.c_double, P(_Lattice)]
+        L.fstat_lattice_nodes.argtypes = [P(_Lattice), P(_LatticeRegion), P(_Ephemeris), vp, vp, i64, P(i64)]
         L.fstat_plan_info.argtypes = [vp, i32, P(i64), P(i64), P(ctypes.c_double), P(i32), P(i32)]
         L.fstat_demod_series.argtypes = [vp, vp, vp, vp]
         L.fstat_profile.argtypes = [vp, i32]
@@ -122,7 +138,8 @@ def lib():
         L.fstat_strerror.restype = ctypes.c_char_p
         L.fstat_destroy.restype = None
         for name in ("fstat_plan", "fstat_grid", "fstat_graph_create", "fstat_graph_launch", "fstat_amplitudes",
-                     "fstat_eval_exact", "fstat_refine", "fstat_threshold",
+                     "fstat_eval_exact", "fstat_refine", "fstat_threshold", "fstat_lattice_fisher",
+                     "fstat_lattice_build", "fstat_lattice_nodes",
                      "fstat_eval", "fstat_adjoint", "fstat_grad", "fstat_plan_info",
                      "fstat_demod_series", "fstat_profile", "fstat_profile_read", "fstat_plan_schedule"):
             getattr(L, name).restype = i32
@@ -193,14 +210,18 @@ def threshold(alpha: float, n_cells: float) -> float:
     return F0.value
 
 
-def nodes_array(alpha, delta, fdot, seg=0) -> np.ndarray:
-    alpha, delta, fdot = np.broadcast_arrays(np.asarray(alpha, float), np.asarray(delta, float),
-                                             np.asarray(fdot, float))
+def nodes_array(alpha, delta, fdot, seg=0, bin_offset=0.0) -> np.ndarray:
+    """Grid nodes (fstat_node records); bin_offset shifts a node's line of
+    Fourier bins by that fraction of a bin (|bin_offset| < 1)."""
+    alpha, delta, fdot, seg, off = np.broadcast_arrays(
+        np.asarray(alpha, float), np.asarray(delta, float), np.asarray(fdot, float),
+        np.asarray(seg, np.int32), np.asarray(bin_offset, np.float32))
     out = np.zeros(alpha.size, dtype=NODE_DTYPE)
     out["alpha"] = alpha.ravel()
     out["delta"] = delta.ravel()
     out["fdot"] = fdot.ravel()
-    out["seg"] = np.broadcast_to(np.asarray(seg, np.int32), alpha.shape).ravel()
+    out["seg"] = seg.ravel()
+    out["bin_offset"] = off.ravel()
     return out
 
 
@@ -210,6 +231,89 @@ def _stream_ptr(device: int) -> ctypes.c_void_p:
 
 def _ptr(t: Optional[torch.Tensor]):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _segment_struct(s: SegmentSpec, keep: list) -> _Segment:
+    seg = _Segment()
+    x = np.ascontiguousarray(np.asarray(s.x, dtype=np.float64))
+    keep.append(x)
+    seg.x = x.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    seg.n = x.size
+    seg.dt = float(s.dt)
+    seg.n_sidereal_days = int(s.n_days)
+    seg.t0 = float(s.t0)
+    if s.mask is not None:
+        m = np.ascontiguousarray(np.asarray(s.mask, dtype=np.uint8))
+        keep.append(m)
+        seg.mask = m.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+    seg.f_ref_hz = float(s.f_ref)
+    seg.sigma2 = float(s.sigma2)
+    seg.nfft = int(s.nfft)
+    return seg
+
+
+def _eph_struct(eph: Ephemeris) -> _Ephemeris:
+    return _Ephemeris(eph.obliquity, eph.orbit_radius, eph.orbit_omega, eph.orbit_phase0, eph.sidereal_day,
+                      eph.gmst0)
+
+
+def lattice_fisher(seg: SegmentSpec, det: Detector, eph: Ephemeris) -> np.ndarray:
+    """Reduced Fisher matrix [4, 4] of the one-spindown linear model over the
+    segment's kept samples (fstat_lattice_fisher: Eq. redFm-def)."""
+    keep: list = []
+    s = _segment_struct(seg, keep)
+    g = (ctypes.c_double * 16)()
+    d = _Detector(det.lat, det.lon, det.gamma, det.zeta, det.radius)
+    e = _eph_struct(eph)
+    _check(lib().fstat_lattice_fisher(ctypes.byref(s), ctypes.byref(d), ctypes.byref(e), g), "fstat_lattice_fisher")
+    return np.array(g[:], dtype=np.float64).reshape(4, 4)
+
+
+class Lattice:
+    """The covering lattice of Sec. IV (fstat_lattice_build) and its grid nodes
+    (fstat_lattice_nodes)."""
+
+    def __init__(self, raw: _Lattice):
+        self._raw = raw
+        self.basis = np.array(raw.basis[:], dtype=np.float64).reshape(4, 4)
+        self.gamma = np.array(raw.gamma[:], dtype=np.float64).reshape(4, 4)
+        for name in ("dp0", "c0", "R", "mu", "nu", "theta", "margin_w1", "margin_sky"):
+            setattr(self, name, float(getattr(raw, name)))
+
+    @classmethod
+    def build(cls, gamma, dp0: float, c0: float = 0.75) -> "Lattice":
+        g = np.ascontiguousarray(np.asarray(gamma, dtype=np.float64).reshape(16))
+        raw = _Lattice()
+        _check(lib().fstat_lattice_build(g.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), float(dp0), float(c0),
+                                         ctypes.byref(raw)), "fstat_lattice_build")
+        return cls(raw)
+
+    @classmethod
+    def for_segment(cls, seg: SegmentSpec, det: Detector, eph: Ephemeris, c0: float = 0.75) -> "Lattice":
+        """The lattice of one segment: its reduced Fisher matrix and the
+        resolution 2 pi / (nfft dt) of its Fourier bins."""
+        nfft = int(seg.nfft) or 1 << int(math.ceil(math.log2(2 * len(seg.x))))
+        return cls.build(lattice_fisher(seg, det, eph), 2 * math.pi / (nfft * seg.dt), c0)
+
+    def nodes(self, f_sky: float, fdot_lo: float, fdot_hi: float, eph: Ephemeris, sky=None, hemisphere: int = 0,
+              seg: int = 0, coef: bool = False):
+        """Grid nodes over the sky disk (or the disk sky = (c1, c2, radius) of
+        the (alpha_1, alpha_2) plane) and [fdot_lo, fdot_hi]: a NODE_DTYPE
+        array, and the lattice coefficients [n, 3] when coef is set."""
+        reg = _LatticeRegion(float(f_sky), float(fdot_lo), float(fdot_hi), 0.0, 0.0, 0.0, int(hemisphere), int(seg))
+        if sky is not None:
+            reg.sky_c1, reg.sky_c2, reg.sky_radius = (float(v) for v in sky)
+        e = _eph_struct(eph)
+        n = ctypes.c_int64()
+        L = lib()
+        _check(L.fstat_lattice_nodes(ctypes.byref(self._raw), ctypes.byref(reg), ctypes.byref(e), None, None, 0,
+                                     ctypes.byref(n)), "fstat_lattice_nodes")
+        out = np.zeros(n.value, dtype=NODE_DTYPE)
+        k = np.zeros((n.value, 3), dtype=np.int32)
+        _check(L.fstat_lattice_nodes(ctypes.byref(self._raw), ctypes.byref(reg), ctypes.byref(e),
+                                     out.ctypes.data_as(ctypes.c_void_p), k.ctypes.data_as(ctypes.c_void_p),
+                                     n.value, ctypes.byref(n)), "fstat_lattice_nodes")
+        return (out, k) if coef else out
 
 
 class Plan:
@@ -222,23 +326,9 @@ class Plan:
         self._keep = []
         segs = (_Segment * len(segments))()
         for i, s in enumerate(segments):
-            x = np.ascontiguousarray(np.asarray(s.x, dtype=np.float64))
-            self._keep.append(x)
-            segs[i].x = x.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
-            segs[i].n = x.size
-            segs[i].dt = float(s.dt)
-            segs[i].n_sidereal_days = int(s.n_days)
-            segs[i].t0 = float(s.t0)
-            if s.mask is not None:
-                m = np.ascontiguousarray(np.asarray(s.mask, dtype=np.uint8))
-                self._keep.append(m)
-                segs[i].mask = m.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
-            segs[i].f_ref_hz = float(s.f_ref)
-            segs[i].sigma2 = float(s.sigma2)
-            segs[i].nfft = int(s.nfft)
+            segs[i] = _segment_struct(s, self._keep)
         d = _Detector(det.lat, det.lon, det.gamma, det.zeta, det.radius)
-        e = _Ephemeris(eph.obliquity, eph.orbit_radius, eph.orbit_omega, eph.orbit_phase0, eph.sidereal_day,
-                       eph.gmst0)
+        e = _eph_struct(eph)
         o = _Options(interp, prec, device, max_batch, 1 if autotune else 0)
         h = ctypes.c_void_p()
         _check(L.fstat_plan(segs, len(segments), ctypes.byref(d), ctypes.byref(e), ctypes.byref(o),

@@ -94,10 +94,14 @@ def test_calls_on_null_plan_are_rejected():
 
 
 def test_node_record_layout_matches_header():
-    # fstat_node: 3 doubles, 2 int32 = 32 bytes; fstat_crossing: 24 bytes
+    # fstat_node: 3 doubles, an int32 and a float = 32 bytes; fstat_crossing: 24 bytes
     assert fstat.NODE_DTYPE.itemsize == 32
+    assert fstat.NODE_DTYPE.fields["bin_offset"][1] == 28
     assert fstat.CROSSING_DTYPE.itemsize == 24
     assert ctypes.sizeof(fstat._Segment) == 72
     assert ctypes.sizeof(fstat._Out) == 80
     # fstat_refine_options: 4 + 1 doubles, 2 int32
     assert ctypes.sizeof(fstat._RefineOptions) == 48
+    # fstat_lattice: 2 x 16 + 8 doubles; fstat_lattice_region: 6 doubles, 2 int32
+    assert ctypes.sizeof(fstat._Lattice) == 320
+    assert ctypes.sizeof(fstat._LatticeRegion) == 56

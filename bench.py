@@ -41,6 +41,10 @@ def parse():
     ap.add_argument("--interbin", action="store_true",
                     help="the same grid with nfft = nextpow2(N) = 2^19 and interbinning (Eq. intbin): F at the "
                          "Fourier bins and the half bins, as many output frequencies as the padded 2^20 map")
+    ap.add_argument("--lattice", choices=("deep_holes", "covering"), default=None,
+                    help="the grid of Sec. IV instead of the uniform one: every node of the constrained A4* "
+                         "lattice over the whole sky and the same spindown range, with its rule for nu; "
+                         "the F map is written 16384 nodes at a time")
     ap.add_argument("--counters", action="store_true",
                     help="short run for hardware-counter collection: one grid call on the first 64 nodes "
                          "and a 1 GiB device copy of known size (the calibration of the byte counters)")
@@ -128,6 +132,18 @@ def workload():
     return w, x, nodes
 
 
+def lattice_workload(w, x, rule):
+    """The full-sky lattice of the segment (Sec. IV, C0 = 3/4) over the uniform
+    grid's spindown range, f_sky at the top of the band."""
+    from paper_1003_0844_amd import fstat, synth
+    spec = fstat.SegmentSpec(x=x, dt=w.dt, n_days=w.days, nfft=w.nfft)
+    r = fstat.NU_COVERING if rule == "covering" else fstat.NU_DEEP_HOLES
+    lat = fstat.Lattice.for_segment(spec, fstat.default_detector(), fstat.Ephemeris(), rule=r)
+    fd = synth.spindown_grid(w.n_fdot)
+    nodes = lat.nodes(synth.F_REF + 1 / (2 * w.dt), float(fd.min()), float(fd.max()), fstat.Ephemeris())
+    return lat, nodes
+
+
 def cpu_baseline(w, x, nodes, budget_s, nfft, ib):
     """The FP64 oracle (resampling method, FP64 numpy FFT for the DFT step) on
     the first nodes of the same grid, until the time budget is used."""
@@ -140,7 +156,8 @@ def cpu_baseline(w, x, nodes, budget_s, nfft, ib):
     done = 0
     for nd in nodes:
         fn = method.fstat_bins_interbinned if ib else method.fstat_bins
-        fn(seg, float(nd["fdot"]), float(nd["alpha"]), float(nd["delta"]), det, eph, method.LINEAR_UP2, dft="fft")
+        fn(seg, float(nd["fdot"]), float(nd["alpha"]), float(nd["delta"]), det, eph, method.LINEAR_UP2, dft="fft",
+           bin_offset=float(nd["bin_offset"]))
         done += 1
         if time.perf_counter() - t0 > budget_s:
             break
@@ -165,7 +182,12 @@ def main():
     from paper_1003_0844_amd import fstat
 
     w, x, nodes = workload()
+    lat = None
+    if args.lattice:
+        lat, nodes = lattice_workload(w, x, args.lattice)
+        log("lattice (%s): theta %.4f, %d nodes" % (args.lattice, lat.theta, len(nodes)))
     nn = len(nodes)
+    chunk = min(nn, 16384)
     ib = bool(args.interbin)
     nfft = (w.nfft // 2) if ib else w.nfft   # interbinning: nextpow2(N) instead of nextpow2(2N)
     half = nfft // 2
@@ -176,18 +198,27 @@ def main():
                       autotune=True)
     sched = plan.schedule()
     log("schedule: %s" % sched)
-    F = torch.empty((nn, width), dtype=torch.float32, device="cuda")
+    F = torch.empty((chunk, width), dtype=torch.float32, device="cuda")
+
+    def step():
+        for c0 in range(0, nn, chunk):
+            part = nodes[c0:c0 + chunk]
+            plan.grid_map(part, 0, half, F[:len(part)], interbin=ib)
+
     for i in range(args.warmup):
-        plan.grid_map(nodes, 0, half, F, interbin=ib)
+        step()
         torch.cuda.synchronize()
         log("warmup step %d done" % i)
     plan.profile(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
-        plan.grid_map(nodes, 0, half, F, interbin=ib)
+        step()
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    if nn > chunk:   # leave the first chunk's map in F for the FP64 comparison
+        plan.grid_map(nodes[:chunk], 0, half, F, interbin=ib)
+        torch.cuda.synchronize()
     log("timed %d steps: %.3f s" % (args.steps, el))
     prof = {k: plan.profile_read(k) for k in (fstat.K_SKY, fstat.K_PASS1, fstat.K_PASS2, fstat.K_OTHER)}
     plan.profile(False)
@@ -226,9 +257,14 @@ def main():
         "value": round(value, 1), "unit": "nodes/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(step_ms, 3), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
-        "config": {"workload": (w.name.replace("nfft=2^20", "nfft=2^19") + ", linear two-step resampling, "
-                                "interbinned F map on bins and half bins of [0, nfft/2)") if ib else
-                               (w.name + ", linear two-step resampling, full F map on bins [0, nfft/2)"),
+        "config": {"workload": ((w.name.replace("nfft=2^20", "nfft=2^19") + ", linear two-step resampling, "
+                                 "interbinned F map on bins and half bins of [0, nfft/2)") if ib else
+                                (w.name + ", linear two-step resampling, full F map on bins [0, nfft/2)"))
+                               if lat is None else
+                               ("2-day segment (N=%d, dt=%g s, nfft=%d), full-sky constrained A4* lattice of "
+                                "Sec. IV (nu rule %s, C0=3/4, theta=%.4f), %d nodes, F map on bins [0, nfft/2) "
+                                "with per-node bin offsets, written 16384 nodes at a time"
+                                % (w.n, w.dt, nfft, args.lattice, lat.theta, nn)),
                    "nodes": nn, "n": w.n, "dt": w.dt, "nfft": nfft, "interbin": ib, "phase": "f64"},
         "roofline": {"bound": "hbm", "kernel": names[dom], "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),

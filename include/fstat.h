@@ -309,12 +309,25 @@ typedef struct {
   double theta;        /* thickness 1.7655 / (mu nu^3) */
   double margin_w1;    /* half-width of a covering ellipsoid's shadow on the omega_1 axis */
   double margin_sky;   /* its largest half-width in the (alpha_1, alpha_2) plane */
+  int32_t rule;        /* the rule for nu it was built with */
+  int32_t reserved;
 } fstat_lattice;
 
-/*   gamma: host [4][4] symmetric positive definite; dp0 > 0; 0 < c0 < 1.
+/* The expansion factor nu.  The paper defines it by the covering radius
+ * staying R; its worked two-dimensional example (nu = sqrt(108 - pi^2)/9,
+ * theta = 1.8171) and the Virgo thickness (about 20 % above A4*) follow
+ * another rule, the largest nu keeping the images of the starting lattice's
+ * deep holes within R.  Both give coverings; the first is thinner (2-D
+ * example: theta 1.219; 2-day segment at nfft = 2^20: 1.838 against 2.094). */
+#define FSTAT_NU_DEEP_HOLES 0  /* the worked example's rule: closed form, microseconds */
+#define FSTAT_NU_COVERING 1    /* the definition: bisection on the covering radius, ~1 s */
+
+/*   gamma: host [4][4] symmetric positive definite; dp0 > 0; 0 < c0 < 1;
+ *   rule: FSTAT_NU_DEEP_HOLES or FSTAT_NU_COVERING.
  * FSTAT_EINVAL: arguments out of range, gamma not positive definite or too
  * ill-conditioned for the constraints to hold to 1e-9. */
-fstat_status fstat_lattice_build(const double gamma[16], double dp0, double c0, fstat_lattice *out);
+fstat_status fstat_lattice_build(const double gamma[16], double dp0, double c0, int32_t rule,
+                                 fstat_lattice *out);
 
 /* A sky region and spindown range to cover. */
 typedef struct {

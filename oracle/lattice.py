@@ -212,19 +212,20 @@ def relevant_vectors(G):
 
 def voronoi_vertices(G):
     """Vertices of the Voronoi cell of the origin: points where d facet planes
-    x.v = |v|^2/2 of relevant vectors v meet and no facet is violated."""
+    x.v = |v|^2/2 of relevant vectors v meet and no facet is violated (every
+    d-subset of facets solved, as one batch)."""
     rv = relevant_vectors(G)
     d = rv.shape[1]
     b = 0.5 * np.einsum("ij,ij->i", rv, rv)
+    idx = np.array(list(itertools.combinations(range(len(rv)), d)))
+    A = rv[idx]
+    ok = np.abs(np.linalg.det(A)) >= 1e-12 * np.prod(np.linalg.norm(A, axis=2), axis=1)
+    X = np.linalg.solve(A[ok], b[idx[ok]][..., None])[..., 0]
+    X = X[np.all(X @ rv.T <= b + 1e-9 * b.max(), axis=1)]
     verts = []
-    for comb in itertools.combinations(range(len(rv)), d):
-        A = rv[list(comb)]
-        if abs(np.linalg.det(A)) < 1e-12 * np.prod(np.linalg.norm(A, axis=1)):
-            continue
-        x = np.linalg.solve(A, b[list(comb)])
-        if np.all(rv @ x <= b + 1e-9 * b.max()):
-            if not any(np.linalg.norm(x - y) < 1e-9 * math.sqrt(b.max()) for y in verts):
-                verts.append(x)
+    for x in X:
+        if not any(np.linalg.norm(x - y) < 1e-9 * math.sqrt(b.max()) for y in verts):
+            verts.append(x)
     return np.array(verts)
 
 
@@ -277,33 +278,80 @@ def expansion_nu(verts, l, mu, R):
     return math.sqrt(float(np.min((R * R - mu * mu * c[ok] ** 2) / p2[ok])))
 
 
-def choose_l(G0, e0_len, R):
+def scaled_generator(G0, l, mu, nu):
+    """G0 O1 diag(mu, nu, ..., nu) O1^-1: shrunk by mu along l and expanded by nu
+    across it."""
+    d = G0.shape[0]
+    O1 = _frame(l / np.linalg.norm(l))
+    return G0 @ O1 @ np.diag([mu] + [nu] * (d - 1)) @ O1.T
+
+
+def covering_nu(G0, l, mu, R, nu_lo, rel_tol=1e-12):
+    """Reading L-nu, rule 'covering' (the paper's definition of nu): the
+    largest nu for which the shrunk and expanded lattice still has covering
+    radius R, by bisection.  The covering radius grows with nu (an expansion
+    never shortens a distance), and nu_lo (the deep-hole rule's value) is a
+    covering."""
+    hi = nu_lo * 1.25
+    while covering_radius(scaled_generator(G0, l, mu, hi)) <= R:
+        nu_lo, hi = hi, hi * 1.25
+    while hi - nu_lo > rel_tol * nu_lo:
+        mid = 0.5 * (nu_lo + hi)
+        if covering_radius(scaled_generator(G0, l, mu, mid)) <= R:
+            nu_lo = mid
+        else:
+            hi = mid
+    return nu_lo
+
+
+def _orbit_key(v, rv):
+    """Sorted |v . r| over the relevant vectors r: equal for vectors that a
+    symmetry of the lattice maps onto each other (it permutes the relevant
+    vectors), which then give congruent constrained lattices."""
+    return tuple(np.round(np.sort(np.abs(rv @ v)), 9))
+
+
+def choose_l(G0, e0_len, R, rule="deep_holes"):
     """Reading L-l: the lattice vector l of the starting lattice with the
-    largest det S = mu nu^(d-1), mu = |e0|/|l|."""
+    largest det S = mu nu^(d-1), mu = |e0|/|l|, nu by the deep-hole rule or
+    (rule 'covering') by the covering radius itself; the latter only over the
+    three shortest admissible lengths, one vector per symmetry class."""
     d = G0.shape[0]
     verts = voronoi_vertices(G0)
     Z = short_vectors(G0, 4 * max(e0_len, R))
     V = Z @ G0
     L = np.linalg.norm(V, axis=1)
+    rv = relevant_vectors(G0)
+    lengths = sorted({round(float(x), 9) for x in L if x >= e0_len * (1 - 1e-12)})
+    seen = set()
     best = None
     for i in np.argsort(L, kind="stable"):
         if L[i] < e0_len * (1 - 1e-12):
             continue
         mu = e0_len / L[i]
         nu = expansion_nu(verts, V[i], mu, R)
+        if rule == "covering":
+            if round(float(L[i]), 9) > lengths[min(2, len(lengths) - 1)]:
+                continue
+            key = _orbit_key(V[i], rv)
+            if key in seen:
+                continue
+            seen.add(key)
+            nu = covering_nu(G0, V[i], mu, R, nu)
         det_s = mu * nu ** (d - 1)
         if best is None or det_s > best["det_s"] * (1 + 1e-12):
             best = dict(z=Z[i], l=V[i], mu=mu, nu=nu, det_s=det_s)
     return best
 
 
-def constrained_generator(G0, M, a0, R, O3=None):
+def constrained_generator(G0, M, a0, R, O3=None, rule="deep_holes", ch=None):
     """Eqs. (opt, opt2): M_opt = M0 O1 S O2^-1 (O3^-1) M^T for the choice of
     choose_l.  Returns the generator (rows in tau coordinates) and the parts."""
     d = G0.shape[0]
     e0 = np.linalg.solve(M, a0)
     e0_len = float(np.linalg.norm(e0))
-    ch = choose_l(G0, e0_len, R)
+    if ch is None:
+        ch = choose_l(G0, e0_len, R, rule)
     O1 = _frame(ch["l"] / np.linalg.norm(ch["l"]))
     O2 = _frame(e0 / e0_len)
     S = np.diag([ch["mu"]] + [ch["nu"]] * (d - 1))
@@ -345,7 +393,7 @@ def _primitive_pair(zl, zf):
     return g == 1
 
 
-def constrained_lattice(G, dp0, c0):
+def constrained_lattice(G, dp0, c0, rule="deep_holes"):
     """The lattice of Sec. IV for the one-spindown linear model (d = 4):
     A4* with covering radius R = sqrt(1 - C0), shrunk and expanded (Eq. opt),
     turned so that a0 = (dp0, 0, 0, 0) is a lattice vector and a second basis
@@ -360,8 +408,9 @@ def constrained_lattice(G, dp0, c0):
     a0 = np.zeros(d)
     a0[0] = dp0
     G0 = generator_a4star(R)
-    base = constrained_generator(G0, M, a0, R)
+    base = constrained_generator(G0, M, a0, R, rule=rule)
     zl = base["z"]
+    ch = {k: base[k] for k in ("z", "l", "mu", "nu", "det_s")}
     # f: shortest vector forming a primitive pair with l (reading L-f)
     Z = short_vectors(G0, 4 * R)
     L = np.linalg.norm(Z @ G0, axis=1)
@@ -372,7 +421,7 @@ def constrained_lattice(G, dp0, c0):
             break
     y = zf @ base["X"]
     O3 = sky_rotation(M, base["e0"], y)
-    full = constrained_generator(G0, M, a0, R, O3=O3)
+    full = constrained_generator(G0, M, a0, R, O3=O3, ch=ch)
     Mopt = full["M_opt"]
     # basis completion (reading L-basis): det[l; f; g; h] = h . cof(l, f, g)
     box = np.array(list(itertools.product(range(-2, 3), repeat=d)), dtype=np.int64)
@@ -395,7 +444,7 @@ def constrained_lattice(G, dp0, c0):
     B[1, 2:] = 0.0
     B = reduce_basis(B)
     return dict(basis=B, R=R, mu=full["mu"], nu=full["nu"], det_s=full["det_s"],
-                theta=THETA_A4STAR / full["det_s"], M=M, M_opt=Mopt, G=G, dp0=dp0, c0=c0)
+                theta=THETA_A4STAR / full["det_s"], M=M, M_opt=Mopt, G=G, dp0=dp0, c0=c0, rule=rule)
 
 
 def reduce_basis(B):

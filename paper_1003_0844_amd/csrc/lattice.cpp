@@ -14,12 +14,16 @@
 //  - the Voronoi cell of a lattice from its relevant vectors (the unique
 //    shortest pairs of the classes of the lattice modulo twice itself) and its
 //    vertices (where four facet planes meet);
-//  - nu: the largest expansion across l that keeps every vertex of the A4*
-//    Voronoi cell (its deep holes), shrunk by mu along l, within R -- a
-//    covering of radius at most R, and the expansion factor of the paper's
-//    worked two-dimensional example;
+//  - nu, rule FSTAT_NU_DEEP_HOLES: the largest expansion across l that keeps
+//    every vertex of the A4* Voronoi cell (its deep holes), shrunk by mu along
+//    l, within R -- a covering of radius at most R, and the expansion factor of
+//    the paper's worked two-dimensional example;
+//    rule FSTAT_NU_COVERING: the paper's definition, the largest nu for which
+//    the covering radius stays R, by bisection from the deep-hole value (the
+//    covering radius grows with nu);
 //  - l: among lattice vectors with |e0| <= |l| <= 4 max(|e0|, R), the largest
-//    det S = mu nu^3;
+//    det S = mu nu^3 (the covering rule: over the three shortest admissible
+//    lengths, one vector per symmetry class of A4*);
 //  - f (Eq. opt2): the shortest lattice vector forming a primitive pair with l;
 //    O3 turns its image, about e0, into M^-1 span(omega_0, omega_1);
 //  - basis: l, f and the first completing pair with coefficients in [-2, 2],
@@ -357,6 +361,56 @@ Mat frame(const Vec& u) {
   return O;
 }
 
+double covering_radius(const Mat& G) {
+  double r = 0.0;
+  for (const Vec& v : voronoi_vertices(G)) r = std::max(r, norm(v));
+  return r;
+}
+
+// G0 O1 diag(mu, nu, nu, nu) O1^T: shrunk by mu along l, expanded by nu across it.
+Mat scaled(const Mat& G0, const Vec& l, double mu, double nu) {
+  Vec lh = l;
+  const double n = norm(l);
+  for (auto& x : lh) x /= n;
+  const Mat O1 = frame(lh);
+  Mat S{};
+  S[0][0] = mu;
+  for (int i = 1; i < D; ++i) S[i][i] = nu;
+  return mul(mul(mul(G0, O1), S), transpose(O1));
+}
+
+double covering_nu(const Mat& G0, const Vec& l, double mu, double R, double lo) {
+  double hi = lo * 1.25;
+  while (covering_radius(scaled(G0, l, mu, hi)) <= R) {
+    lo = hi;
+    hi *= 1.25;
+  }
+  while (hi - lo > 1e-12 * lo) {
+    const double mid = 0.5 * (lo + hi);
+    if (covering_radius(scaled(G0, l, mu, mid)) <= R)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+// Sorted |v . r| over the relevant vectors: shared by vectors a symmetry of the
+// lattice maps onto each other (it permutes the relevant vectors).
+std::vector<double> orbit_key(const Vec& v, const std::vector<Vec>& rv) {
+  std::vector<double> k;
+  for (const Vec& r : rv) k.push_back(std::fabs(dot(v, r)));
+  std::sort(k.begin(), k.end());
+  return k;
+}
+
+bool same_key(const std::vector<double>& a, const std::vector<double>& b) {
+  if (a.size() != b.size()) return false;
+  for (size_t i = 0; i < a.size(); ++i)
+    if (std::fabs(a[i] - b[i]) > 1e-9 * (1.0 + std::fabs(a[i]))) return false;
+  return true;
+}
+
 double expansion_nu(const std::vector<Vec>& verts, const Vec& l, double mu, double R) {
   Vec lh = l;
   const double ln = norm(l);
@@ -429,9 +483,9 @@ fstat_status fstat_lattice_fisher(const fstat_segment* seg, const fstat_detector
   return FSTAT_OK;
 }
 
-fstat_status fstat_lattice_build(const double gamma[16], double dp0, double c0, fstat_lattice* out) {
+fstat_status fstat_lattice_build(const double gamma[16], double dp0, double c0, int32_t rule, fstat_lattice* out) {
   if (!gamma || !out || !finite_all(gamma, 16) || !(dp0 > 0.0) || !std::isfinite(dp0) || !(c0 > 0.0) ||
-      !(c0 < 1.0))
+      !(c0 < 1.0) || (rule != FSTAT_NU_DEEP_HOLES && rule != FSTAT_NU_COVERING))
     return FSTAT_EINVAL;
   Mat G{};
   for (int i = 0; i < D; ++i)
@@ -472,10 +526,25 @@ fstat_status fstat_lattice_build(const double gamma[16], double dp0, double c0, 
   std::stable_sort(ord.begin(), ord.end(), [&](size_t a, size_t b) { return len[a] < len[b]; });
   double best = -1.0, mu = 0.0, nu = 0.0;
   IVec zl{};
+  std::vector<double> lengths;  // distinct admissible lengths, ascending
+  for (size_t i : ord)
+    if (len[i] >= e0n * (1 - 1e-12) && (lengths.empty() || len[i] > lengths.back() * (1 + 1e-9)))
+      lengths.push_back(len[i]);
+  const std::vector<Vec> rv = relevant_vectors(G0);
+  std::vector<std::vector<double>> seen;
   for (size_t i : ord) {
     if (len[i] < e0n * (1 - 1e-12)) continue;
     const double m_ = e0n / len[i];
-    const double n_ = expansion_nu(verts, combo(cand[i], G0), m_, R);
+    double n_ = expansion_nu(verts, combo(cand[i], G0), m_, R);
+    if (rule == FSTAT_NU_COVERING) {
+      if (lengths.empty() || len[i] > lengths[std::min<size_t>(2, lengths.size() - 1)] * (1 + 1e-9)) continue;
+      const std::vector<double> key = orbit_key(combo(cand[i], G0), rv);
+      bool dup = false;
+      for (const auto& k : seen) dup = dup || same_key(k, key);
+      if (dup) continue;
+      seen.push_back(key);
+      n_ = covering_nu(G0, combo(cand[i], G0), m_, R, n_);
+    }
     const double ds = m_ * n_ * n_ * n_;
     if (ds > best * (1 + 1e-12)) {
       best = ds;
@@ -642,6 +711,8 @@ fstat_status fstat_lattice_build(const double gamma[16], double dp0, double c0, 
   out->theta = THETA_A4STAR / best;
   out->margin_w1 = R * std::sqrt(Gi[1][1]);
   out->margin_sky = R * std::sqrt(lmax);
+  out->rule = rule;
+  out->reserved = 0;
   return FSTAT_OK;
 }
 

@@ -57,7 +57,8 @@ class _Ephemeris(ctypes.Structure):
 class _Lattice(ctypes.Structure):
     _fields_ = [("basis", ctypes.c_double * 16), ("gamma", ctypes.c_double * 16), ("dp0", ctypes.c_double),
                 ("c0", ctypes.c_double), ("R", ctypes.c_double), ("mu", ctypes.c_double), ("nu", ctypes.c_double),
-                ("theta", ctypes.c_double), ("margin_w1", ctypes.c_double), ("margin_sky", ctypes.c_double)]
+                ("theta", ctypes.c_double), ("margin_w1", ctypes.c_double), ("margin_sky", ctypes.c_double),
+                ("rule", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class _LatticeRegion(ctypes.Structure):
@@ -100,6 +101,7 @@ EXPORTS = ("fstat_plan", "fstat_grid", "fstat_graph_create", "fstat_graph_launch
            "fstat_profile",
            "fstat_profile_read", "fstat_plan_schedule", "fstat_destroy", "fstat_strerror")
 K_SKY, K_PASS1, K_PASS2, K_OTHER = 0, 1, 2, 3
+NU_DEEP_HOLES, NU_COVERING = 0, 1
 
 _lib = None
 
@@ -126,7 +128,7 @@ def lib():
         L.fstat_refine.argtypes = [vp, vp, vp, i64, P(_RefineOptions), vp, vp, vp, vp]
         L.fstat_threshold.argtypes = [ctypes.c_double, ctypes.c_double, P(ctypes.c_double)]
         L.fstat_lattice_fisher.argtypes = [P(_Segment), P(_Detector), P(_Ephemeris), P(ctypes.c_double)]
-        L.fstat_lattice_build.argtypes = [P(ctypes.c_double), ctypes.c_double, ctypes.c_double, P(_Lattice)]
+        L.fstat_lattice_build.argtypes = [P(ctypes.c_double), ctypes.c_double, ctypes.c_double, i32, P(_Lattice)]
         L.fstat_lattice_nodes.argtypes = [P(_Lattice), P(_LatticeRegion), P(_Ephemeris), vp, vp, i64, P(i64)]
         L.fstat_plan_info.argtypes = [vp, i32, P(i64), P(i64), P(ctypes.c_double), P(i32), P(i32)]
         L.fstat_demod_series.argtypes = [vp, vp, vp, vp]
@@ -279,21 +281,25 @@ class Lattice:
         self.gamma = np.array(raw.gamma[:], dtype=np.float64).reshape(4, 4)
         for name in ("dp0", "c0", "R", "mu", "nu", "theta", "margin_w1", "margin_sky"):
             setattr(self, name, float(getattr(raw, name)))
+        self.rule = int(raw.rule)
 
     @classmethod
-    def build(cls, gamma, dp0: float, c0: float = 0.75) -> "Lattice":
+    def build(cls, gamma, dp0: float, c0: float = 0.75, rule: int = NU_DEEP_HOLES) -> "Lattice":
+        """rule NU_DEEP_HOLES: the paper's worked example; NU_COVERING: its
+        definition of nu, a thinner covering (fstat_lattice_build)."""
         g = np.ascontiguousarray(np.asarray(gamma, dtype=np.float64).reshape(16))
         raw = _Lattice()
         _check(lib().fstat_lattice_build(g.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), float(dp0), float(c0),
-                                         ctypes.byref(raw)), "fstat_lattice_build")
+                                         int(rule), ctypes.byref(raw)), "fstat_lattice_build")
         return cls(raw)
 
     @classmethod
-    def for_segment(cls, seg: SegmentSpec, det: Detector, eph: Ephemeris, c0: float = 0.75) -> "Lattice":
+    def for_segment(cls, seg: SegmentSpec, det: Detector, eph: Ephemeris, c0: float = 0.75,
+                    rule: int = NU_DEEP_HOLES) -> "Lattice":
         """The lattice of one segment: its reduced Fisher matrix and the
         resolution 2 pi / (nfft dt) of its Fourier bins."""
         nfft = int(seg.nfft) or 1 << int(math.ceil(math.log2(2 * len(seg.x))))
-        return cls.build(lattice_fisher(seg, det, eph), 2 * math.pi / (nfft * seg.dt), c0)
+        return cls.build(lattice_fisher(seg, det, eph), 2 * math.pi / (nfft * seg.dt), c0, rule)
 
     def nodes(self, f_sky: float, fdot_lo: float, fdot_hi: float, eph: Ephemeris, sky=None, hemisphere: int = 0,
               seg: int = 0, coef: bool = False):

@@ -102,6 +102,6 @@ def test_node_record_layout_matches_header():
     assert ctypes.sizeof(fstat._Out) == 80
     # fstat_refine_options: 4 + 1 doubles, 2 int32
     assert ctypes.sizeof(fstat._RefineOptions) == 48
-    # fstat_lattice: 2 x 16 + 8 doubles; fstat_lattice_region: 6 doubles, 2 int32
-    assert ctypes.sizeof(fstat._Lattice) == 320
+    # fstat_lattice: 2 x 16 + 8 doubles, 2 int32; fstat_lattice_region: 6 doubles, 2 int32
+    assert ctypes.sizeof(fstat._Lattice) == 328
     assert ctypes.sizeof(fstat._LatticeRegion) == 56

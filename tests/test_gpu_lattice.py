@@ -70,8 +70,9 @@ def test_bin_offset_is_validated():
         assert e.value.status == fstat.EINVAL
 
 
+@pytest.mark.parametrize("rule", [fstat.NU_DEEP_HOLES, fstat.NU_COVERING])
 @pytest.mark.parametrize("seed", [31, 32, 33])
-def test_lattice_patch_search_recovers_a_signal(seed):
+def test_lattice_patch_search_recovers_a_signal(seed, rule):
     # a noise-free signal; the library's lattice nodes over a sky patch of
     # half a sky cell around it and its spindown: the covering (correlation
     # C0 = 3/4 in the linear model) keeps the best node near 3/4 of the
@@ -81,7 +82,7 @@ def test_lattice_patch_search_recovers_a_signal(seed):
     sig = one_signal(seed, band=band, snr=20.0, fdot=(-4e-10, 0.0))
     seg = small_segment(days=1, dt=dt, seed=seed, signal=sig, noise=False)
     spec = fstat.SegmentSpec(x=seg.x, dt=dt, n_days=1, t0=seg.t0, f_ref=seg.f_ref, sigma2=seg.sigma2)
-    lat = fstat.Lattice.for_segment(spec, fstat.detector_spec(DET), fstat.ephemeris_spec(EPH))
+    lat = fstat.Lattice.for_segment(spec, fstat.detector_spec(DET), fstat.ephemeris_spec(EPH), rule=rule)
     f_sky = seg.f_ref + band
     om = 2 * math.pi * f_sky
     ce, se = math.cos(EPH.obliquity), math.sin(EPH.obliquity)
@@ -92,7 +93,7 @@ def test_lattice_patch_search_recovers_a_signal(seed):
     cell = math.sqrt(abs(np.linalg.det(lat.basis[2:, 2:])))
     nodes = lat.nodes(f_sky, sig["fdot"], sig["fdot"], fstat.ephemeris_spec(EPH), sky=(a1, a2, 0.5 * cell),
                       hemisphere=1 if nz >= 0 else -1)
-    banner("lattice patch search", "seed", seed, "nodes", len(nodes), "theta", lat.theta)
+    banner("lattice patch search", "seed", seed, "rule", rule, "nodes", len(nodes), "theta", lat.theta)
     assert 8 <= len(nodes) <= 200
     plan = make_plan([seg], method.LINEAR_UP2, fstat.FP32)
     half = seg.fft_len // 2

@@ -145,20 +145,20 @@ def test_lattice_argument_checks(both):
     g = np.ascontiguousarray(lat.gamma.reshape(16))
     out = fstat._Lattice()
     gp = g.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
-    assert L_.fstat_lattice_build(gp, lat.dp0, 0.75, ctypes.byref(out)) == fstat.OK
-    assert L_.fstat_lattice_build(gp, lat.dp0, 1.0, ctypes.byref(out)) == fstat.EINVAL
-    assert L_.fstat_lattice_build(gp, lat.dp0, 0.0, ctypes.byref(out)) == fstat.EINVAL
-    assert L_.fstat_lattice_build(gp, -lat.dp0, 0.75, ctypes.byref(out)) == fstat.EINVAL
-    assert L_.fstat_lattice_build(gp, lat.dp0, 0.75, None) == fstat.EINVAL
+    assert L_.fstat_lattice_build(gp, lat.dp0, 0.75, 0, ctypes.byref(out)) == fstat.OK
+    assert L_.fstat_lattice_build(gp, lat.dp0, 1.0, 0, ctypes.byref(out)) == fstat.EINVAL
+    assert L_.fstat_lattice_build(gp, lat.dp0, 0.0, 0, ctypes.byref(out)) == fstat.EINVAL
+    assert L_.fstat_lattice_build(gp, -lat.dp0, 0.75, 0, ctypes.byref(out)) == fstat.EINVAL
+    assert L_.fstat_lattice_build(gp, lat.dp0, 0.75, 0, None) == fstat.EINVAL
     bad = g.copy()
     bad[1] *= 1.5                                   # not symmetric
-    assert L_.fstat_lattice_build(bad.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), lat.dp0, 0.75,
+    assert L_.fstat_lattice_build(bad.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), lat.dp0, 0.75, 0,
                                   ctypes.byref(out)) == fstat.EINVAL
     indef = np.diag([1.0, 1.0, 1.0, -1.0]).reshape(16)
-    assert L_.fstat_lattice_build(indef.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 1.0, 0.75,
+    assert L_.fstat_lattice_build(indef.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 1.0, 0.75, 0,
                                   ctypes.byref(out)) == fstat.EINVAL
     sing = np.ones(16)                               # rank one
-    assert L_.fstat_lattice_build(sing.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 1.0, 0.75,
+    assert L_.fstat_lattice_build(sing.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 1.0, 0.75, 0,
                                   ctypes.byref(out)) == fstat.EINVAL
     e = fstat._eph_struct(FEPH)
     n = ctypes.c_int64()
@@ -189,3 +189,20 @@ def test_lattice_for_several_segments(days, dt, t0):
         assert abs(getattr(lat, name) - lo[name]) < 1e-10 * abs(lo[name]), name
     X = np.linalg.solve(lo["M"], lat.basis.T).T
     assert L.covering_radius(X) <= lat.R * (1 + 1e-9)
+
+
+def test_covering_rule_matches_oracle(both):
+    lat0, _ = both
+    lat = fstat.Lattice.build(lat0.gamma, lat0.dp0, 0.75, rule=fstat.NU_COVERING)
+    assert lat.rule == fstat.NU_COVERING
+    lo = L.constrained_lattice(lat0.gamma, lat0.dp0, 0.75, rule="covering")
+    for name in ("mu", "nu", "theta"):
+        assert abs(getattr(lat, name) - lo[name]) < 1e-9 * abs(lo[name]), name
+    X = np.linalg.solve(lo["M"], lat.basis.T).T
+    cr = L.covering_radius(X)
+    assert lat.R * (1 - 1e-9) <= cr <= lat.R * (1 + 1e-9)
+    assert lat.theta < lat0.theta
+    g = np.ascontiguousarray(lat0.gamma.reshape(16))
+    out = fstat._Lattice()
+    assert fstat.lib().fstat_lattice_build(g.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), lat0.dp0, 0.75, 2,
+                                           ctypes.byref(out)) == fstat.EINVAL

@@ -266,3 +266,32 @@ def test_offset_bins_are_the_continuous_transform():
     F0, Fh = method.fstat_bins_interbinned(seg, fd, al, de, DET, EPH, method.LINEAR_UP2, k=k, bin_offset=0.4)
     assert np.allclose(F0, method.fstat_bins(seg, fd, al, de, DET, EPH, method.LINEAR_UP2, k=k, bin_offset=0.4),
                        rtol=1e-12, atol=1e-12)
+
+
+def test_covering_rule_on_the_2d_example():
+    # nu by the paper's definition (the covering radius stays R).  The shrunk
+    # hexagonal lattice is centred-rectangular with half sides a = 3 mu/4 along
+    # l and b = sqrt(3) nu/4 across it; once b > a its deep holes are the
+    # circumcentres of the triangles (0, (2a, 0), (a, b)) at distance
+    # (a^2 + b^2)/(2b), so covering radius R gives b = R + sqrt(R^2 - a^2).
+    M = L.whitening(G2D)
+    r = L.constrained_generator(L.generator_a2star(R), M, np.array([math.pi, 0.0]), R, rule="covering")
+    mu = math.pi / (3 * math.sqrt(3))
+    a = 3 * mu / 4
+    b = R + math.sqrt(R * R - a * a)
+    assert abs(r["mu"] - mu) < 1e-13
+    assert abs(r["nu"] - 4 * b / math.sqrt(3)) < 1e-9
+    assert abs(L.covering_radius(r["X"]) - R) < 1e-9 and L.covering_radius(r["X"]) <= R * (1 + 1e-12)
+    theta = L.thickness(r["X"], R)
+    assert abs(theta - L.thickness(L.generator_a2star(R), R) / (mu * r["nu"])) < 1e-9
+    assert theta < 0.7 * GOLD["lattice_2d_theta"]["value"]      # 1.2186 against the printed 1.8171
+
+
+def test_covering_rule_in_four_dimensions(lat4):
+    lat = L.constrained_lattice(lat4["G"], lat4["dp0"], 0.75, rule="covering")
+    X = np.linalg.solve(lat["M"], lat["basis"].T).T
+    cr = L.covering_radius(X)
+    assert cr <= lat["R"] * (1 + 1e-9) and cr >= lat["R"] * (1 - 1e-9)
+    assert lat["theta"] < lat4["theta"] and lat["nu"] >= lat4["nu"]
+    assert abs(L.thickness(X, lat["R"]) - L.thickness(L.generator_a4star(lat["R"]), lat["R"]) / lat["det_s"]) < 1e-9
+    assert np.all(lat["basis"][0, 1:] == 0) and np.all(lat["basis"][1, 2:] == 0)

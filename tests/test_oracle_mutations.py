@@ -179,3 +179,17 @@ def test_dropped_diurnal_term_of_mu1_is_caught(monkeypatch):
 def test_unshifted_bins_are_caught(monkeypatch):
     monkeypatch.setattr(method, "shift_bins", lambda z, nfft, off: z)
     _fails(tl.test_offset_bins_are_the_continuous_transform)
+
+
+def test_reversed_bisection_of_the_covering_rule_is_caught(monkeypatch):
+    def bad(G0, l, mu, R, nu_lo, rel_tol=1e-12):
+        hi = nu_lo * 1.25
+        for _ in range(60):
+            mid = 0.5 * (nu_lo + hi)
+            if lat_oracle.covering_radius(lat_oracle.scaled_generator(G0, l, mu, mid)) <= R:
+                hi = mid                               # keeps the lower end
+            else:
+                nu_lo = mid
+        return nu_lo
+    monkeypatch.setattr(lat_oracle, "covering_nu", bad)
+    _fails(tl.test_covering_rule_on_the_2d_example)

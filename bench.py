@@ -46,24 +46,28 @@ def parse():
                          "lattice over the whole sky and the same spindown range, with its rule for nu; "
                          "the F map is written 16384 nodes at a time")
     ap.add_argument("--counters", action="store_true",
-                    help="short run for hardware-counter collection: one grid call on the first 64 nodes "
+                    help="short run for hardware-counter collection: one grid call on two node batches "
+                         "of the benchmark's (autotuned) schedule "
                          "and a 1 GiB device copy of known size (the calibration of the byte counters)")
     return ap.parse_args()
 
 
 def counters_run(args):
-    """One grid call on 4 sky positions x 16 spindowns, then a plain copy of
-    exactly 2^30 bytes: the copy's FETCH_SIZE / WRITE_SIZE readings give the
-    scale from counter units to bytes moved."""
+    """One grid call on two node batches of the benchmark's schedule, then a
+    plain copy of exactly 2^30 bytes: the copy's FETCH_SIZE / WRITE_SIZE
+    readings give the scale from counter units to bytes moved."""
     import torch
     from paper_1003_0844_amd import fstat
     w, x, nodes = workload()
-    sub = nodes[:64]
     ib = bool(args.interbin)
     nfft = (w.nfft // 2) if ib else w.nfft
     half = nfft // 2
+    # the benchmark's schedule: autotuned (read back from FSTAT_TUNE_CACHE when
+    # the benchmark run wrote it there) or the given batch
     plan = fstat.Plan([fstat.SegmentSpec(x=x, dt=w.dt, n_days=w.days, nfft=nfft)], fstat.default_detector(),
-                      fstat.Ephemeris(), interp=fstat.LINEAR_UP2, prec=fstat.FP32, max_batch=args.max_batch)
+                      fstat.Ephemeris(), interp=fstat.LINEAR_UP2, prec=fstat.FP32, max_batch=args.max_batch,
+                      autotune=True)
+    sub = nodes[:2 * plan.schedule()["batch"]]
     F = torch.empty((len(sub), (2 if ib else 1) * half), dtype=torch.float32, device="cuda")
     plan.grid_map(sub, 0, half, F, interbin=ib)
     torch.cuda.synchronize()

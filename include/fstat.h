@@ -112,8 +112,8 @@ typedef struct {
   int32_t max_batch; /* nodes per FFT batch; 0 = library default (or the tuned value) */
   int32_t autotune;  /* 1: at plan time, time the candidate FFT splits nfft = R x C
                         (C = 1024, 2048, 4096 columns where valid) and node-batch sizes
-                        (FP32: 8, 16, 32; FP64: 2, 4, 8) of every segment on a sample
-                        grid of 8 sky positions x 16 spindowns and keep the fastest (the
+                        (FP32: 32, 64, 128; FP64: 2, 4, 8) of every segment on a sample
+                        grid of 64 sky positions x 16 spindowns and keep the fastest (the
                         default schedule unless another is at least 3 % faster); one
                         tuning per distinct (n, nfft), shared by the segments of that
                         size.  The choice is cached in the file named by the

@@ -582,7 +582,7 @@ bool cache_lookup(const TuneKey& k, int& C, int& batch) {
   while (std::fgets(line, sizeof line, f)) {
     int pr, ip, c, b;
     long long nf, nn;
-    if (std::sscanf(line, "fstat-tune-v1 %d %d %lld %lld %d %d", &pr, &ip, &nf, &nn, &c, &b) == 6 && pr == k.prec &&
+    if (std::sscanf(line, "fstat-tune-v2 %d %d %lld %lld %d %d", &pr, &ip, &nf, &nn, &c, &b) == 6 && pr == k.prec &&
         ip == k.interp && nf == k.nfft && nn == k.n) {
       C = c;
       batch = b;
@@ -598,7 +598,7 @@ void cache_store(const TuneKey& k, int C, int batch) {
   if (!path || !*path) return;
   FILE* f = std::fopen(path, "a");
   if (!f) return;
-  std::fprintf(f, "fstat-tune-v1 %d %d %lld %lld %d %d\n", k.prec, k.interp, (long long)k.nfft, (long long)k.n, C,
+  std::fprintf(f, "fstat-tune-v2 %d %d %lld %lld %d %d\n", k.prec, k.interp, (long long)k.nfft, (long long)k.n, C,
                batch);
   std::fclose(f);
 }
@@ -627,15 +627,15 @@ fstat_status tune_segment(fstat_plan_s* p, int si) {
     if (split_valid(prec, nfft, c) && std::find(cands.begin(), cands.end(), c) == cands.end()) cands.push_back(c);
   std::vector<int> batches;
   if (p->max_batch > 0) batches = {p->max_batch};
-  else if (prec == 0) batches = {32, 16, 8};
+  else if (prec == 0) batches = {128, 64, 32};
   else batches = {8, 4, 2};
-  const int nsky = 8, nfd = 16;
+  const int nsky = 64, nfd = 16;
   std::vector<fstat_node> nodes(nsky * nfd);
   for (int s = 0; s < nsky; ++s)
     for (int f = 0; f < nfd; ++f) {
       fstat_node& nd = nodes[s * nfd + f];
-      nd.alpha = 0.4 + 0.8 * s;
-      nd.delta = -1.2 + 0.3 * s;
+      nd.alpha = 0.4 + 0.09 * s;
+      nd.delta = -1.2 + 2.4 * s / (nsky - 1);
       nd.fdot = -1e-9 * f / (nfd - 1);
       nd.seg = si;
       nd.bin_offset = 0.0f;

@@ -39,6 +39,32 @@ struct Pair {
 
 template <typename T>
 __device__ __forceinline__ cpx<T> twmul(cpx<T> v, cpx<T> w) { return cmul(v, w); }
+
+// Streaming (non-temporal) access for data a pass touches once: the
+// inter-pass spill written by pass 1 and read once by pass 2, and the F map.
+// With both passes in flight this keeps them from displacing each other's
+// cached lines (the 2-day grid: +9 % at equal batch, +16 % with the larger
+// batches it makes the best choice).
+template <typename T>
+__device__ __forceinline__ Pair<T> load_stream(const Pair<T>* p) {
+  typedef T v4 __attribute__((ext_vector_type(4)));
+  const v4 w = __builtin_nontemporal_load(reinterpret_cast<const v4*>(p));
+  return Pair<T>{{w.x, w.y}, {w.z, w.w}};
+}
+template <typename T>
+__device__ __forceinline__ void store_stream(Pair<T>* p, const Pair<T>& v) {
+  typedef T v4 __attribute__((ext_vector_type(4)));
+  v4 w;
+  w.x = v.a.x;
+  w.y = v.a.y;
+  w.z = v.b.x;
+  w.w = v.b.y;
+  __builtin_nontemporal_store(w, reinterpret_cast<v4*>(p));
+}
+template <typename T>
+__device__ __forceinline__ void store_stream(T* p, T v) {
+  __builtin_nontemporal_store(v, p);
+}
 template <typename T>
 __device__ __forceinline__ Pair<T> twmul(Pair<T> v, cpx<T> w) { return {cmul(v.a, w), cmul(v.b, w)}; }
 

@@ -68,7 +68,7 @@ k_pass1(SegDev sg, const Quad<T>* __restrict__ quads, int64_t qstride, const Sky
     cpx<T> pw[RS];
     powers<RS>(step, pw);
 #pragma unroll
-    for (int q = 0; q < RS; ++q) dst[i + q * STR] = twmul(v[q], cmul(base, pw[q]));
+    for (int q = 0; q < RS; ++q) store_stream(&dst[i + q * STR], twmul(v[q], cmul(base, pw[q])));
   };
   block_fft<Pair<T>, C, 1, BLOCK, -1>(lds, twC, load, store);
 }
@@ -87,7 +87,7 @@ k_pass2(SegDev sg, const Pair<T>* __restrict__ spill, const NodeDev* __restrict_
   const NodeDev node = nodes[nd];
   const int C = sg.C;
   const Pair<T>* __restrict__ src = spill + (int64_t)nd * sg.nfft + (int64_t)cb * B2;
-  auto load = [&](int r, int col) -> Pair<T> { return src[(int64_t)r * C + col]; };
+  auto load = [&](int r, int col) -> Pair<T> { return load_stream(&src[(int64_t)r * C + col]); };
   const SkyCoef cf = coef[node.sky];
   const T cB = (T)cf.cB, cA = (T)cf.cA, cC = (T)cf.cC;
   const int64_t klo = out.k_lo, khi = out.k_hi;
@@ -103,7 +103,7 @@ k_pass2(SegDev sg, const Pair<T>* __restrict__ spill, const NodeDev* __restrict_
     const T re = fma(v.a.x, v.b.x, v.a.y * v.b.y);
     const T F = fma(cB, pa, fma(cA, pb, -(cC * re)));
     if constexpr (MODE == 0) {
-      ((T*)out.F)[(int64_t)node.row * (khi - klo) + (k - klo)] = F;
+      store_stream(&((T*)out.F)[(int64_t)node.row * (khi - klo) + (k - klo)], F);
     } else if constexpr (MODE == 1) {
       const double f = (double)F;
       if (f > best || (f == best && k < bestk)) {
@@ -188,6 +188,8 @@ k_pass2_ib(SegDev sg, const Pair<T>* __restrict__ spill, const NodeDev* __restri
   const bool wrap = k2_0 + B2 == C;
   const int k2_x = wrap ? 0 : k2_0 + B2;
   const Pair<T>* __restrict__ src = spill + (int64_t)nd * sg.nfft;
+  // ordinary loads: the extra column is read by the neighbouring workgroup
+  // too, and with streaming loads this kernel runs 25-30 % slower (measured)
   auto load = [&](int r, int col) -> Pair<T> { return src[(int64_t)r * C + (col < B2 ? k2_0 + col : k2_x)]; };
   Pair<T> fin[GL::PER][GL::Rs];
   auto keep = [&](int, int, auto& v, auto, int m) {
@@ -227,7 +229,7 @@ k_pass2_ib(SegDev sg, const Pair<T>* __restrict__ spill, const NodeDev* __restri
   auto emit = [&](int64_t k, int h, T F) {
     const int64_t kh = 2 * k + h;
     if constexpr (MODE == 0) {
-      ((T*)out.F)[(int64_t)node.row * 2 * (khi - klo) + (kh - 2 * klo)] = F;
+      store_stream(&((T*)out.F)[(int64_t)node.row * 2 * (khi - klo) + (kh - 2 * klo)], F);
     } else if constexpr (MODE == 1) {
       const double f = (double)F;
       if (f > best || (f == best && kh < bestk)) {

@@ -242,8 +242,8 @@ def test_autotuned_plan_and_cache(tmp_path, monkeypatch):
     plan = fstat.Plan(specs, fstat.detector_spec(DET), fstat.ephemeris_spec(EPH), interp=w.interp,
                       prec=fstat.FP32, autotune=True)
     sch = plan.schedule()
-    assert sch["C"] in (1024, 2048, 4096) and sch["R"] * sch["C"] == w.nfft and sch["batch"] in (8, 16, 32)
-    assert cache.read_text().startswith("fstat-tune-v1")
+    assert sch["C"] in (1024, 2048, 4096) and sch["R"] * sch["C"] == w.nfft and sch["batch"] in (32, 64, 128)
+    assert cache.read_text().startswith("fstat-tune-v2")
     nodes = fstat.nodes_array(np.full(3, p["alpha"]), np.full(3, p["delta"]), [p["fdot"], 0.0, -5e-10])
     F = plan.grid_map(nodes, 0, w.nfft // 2).cpu().numpy()
     for i, nd in enumerate(nodes):
@@ -261,7 +261,7 @@ def test_every_split_gives_the_same_map(C, tmp_path, monkeypatch):
     w = synth.TINY
     g, x, sigs = synth.segment_data(w)
     cache = tmp_path / "tune.txt"
-    cache.write_text("fstat-tune-v1 0 %d %d %d %d 8\n" % (w.interp, w.nfft, w.n, C))
+    cache.write_text("fstat-tune-v2 0 %d %d %d %d 8\n" % (w.interp, w.nfft, w.n, C))
     monkeypatch.setenv("FSTAT_TUNE_CACHE", str(cache))
     banner("split", C)
     specs = [fstat.SegmentSpec(x=x, dt=w.dt, n_days=w.days, f_ref=synth.F_REF, sigma2=1.0, nfft=w.nfft)]

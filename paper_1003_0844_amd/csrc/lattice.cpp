@@ -338,20 +338,29 @@ std::vector<Vec> voronoi_vertices(const Mat& G) {
   return verts;
 }
 
-// An orthogonal matrix (column convention) whose first column is the unit vector u.
+// An orthogonal matrix (column convention) whose first column is the unit vector u:
+// Gram-Schmidt on the coordinate axes, each time the axis farthest from the span so
+// far (with m < 4 orthonormal columns some axis keeps a residual of at least 1/2).
 Mat frame(const Vec& u) {
   std::vector<Vec> cols{u};
-  for (int e = 0; e < D && (int)cols.size() < D; ++e) {
-    Vec w{};
-    w[e] = 1.0;
-    for (const Vec& c : cols) {
-      const double p = dot(w, c);
-      for (int k = 0; k < D; ++k) w[k] -= p * c[k];
+  while ((int)cols.size() < D) {
+    Vec best{};
+    double bn = -1.0;
+    for (int e = 0; e < D; ++e) {
+      Vec w{};
+      w[e] = 1.0;
+      for (const Vec& c : cols) {
+        const double p = dot(w, c);
+        for (int k = 0; k < D; ++k) w[k] -= p * c[k];
+      }
+      const double n = norm(w);
+      if (n > bn) {
+        bn = n;
+        best = w;
+      }
     }
-    const double n = norm(w);
-    if (n < 0.3) continue;  // too close to the span so far; another axis will do
-    for (auto& x : w) x /= n;
-    cols.push_back(w);
+    for (auto& x : best) x /= bn;
+    cols.push_back(best);
   }
   Mat O{};
   for (int j = 0; j < D; ++j)

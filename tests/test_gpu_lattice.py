@@ -5,6 +5,7 @@ import math
 
 import numpy as np
 import pytest
+import torch
 
 from oracle import method
 from paper_1003_0844_amd import fstat, synth
@@ -148,3 +149,30 @@ def test_lattice_nodes_at_full_size_sampled_bins():
         assert f_error(Fh[i][k], ref) < PREC_TOL[fstat.FP32], i
     # the SNR-10 injection stands out at the best node (2F ~ 4 in noise)
     assert 2 * Fh.max() > 40
+
+
+@pytest.mark.parametrize("interbin", [False, True])
+def test_graph_replays_of_offset_nodes(interbin):
+    # lattice nodes (bin offsets) recorded as a HIP graph: every replay equal to
+    # the eager call, with eager work between replays
+    dt = 13.0
+    sig = one_signal(44, band=1 / (2 * dt), snr=15.0)
+    seg = small_segment(days=1, dt=dt, seed=44, signal=sig)
+    spec = fstat.SegmentSpec(x=seg.x, dt=dt, n_days=1, t0=seg.t0, f_ref=seg.f_ref, sigma2=seg.sigma2)
+    lat = fstat.Lattice.for_segment(spec, fstat.detector_spec(DET), fstat.ephemeris_spec(EPH))
+    f_sky = seg.f_ref + 1 / (2 * dt)
+    nodes = lat.nodes(f_sky, -3e-10, 0.0, fstat.ephemeris_spec(EPH), sky=(0.2 * 2 * math.pi * f_sky, 0.1, 150.0))
+    banner("lattice graph", "interbin", interbin, "nodes", len(nodes))
+    assert len(nodes) > 4 and np.any(nodes["bin_offset"] != 0)
+    plan = make_plan([seg], method.LINEAR_UP2, fstat.FP32, max_batch=4)
+    half = seg.fft_len // 2 - (1 if interbin else 0)
+    eager = plan.grid_map(nodes, 0, half, interbin=interbin).clone()
+    g = plan.graph_map(nodes, 0, half, interbin=interbin)
+    for rep in range(3):
+        g.outputs["F"].fill_(float("nan"))
+        g.launch()
+        torch.cuda.synchronize()
+        assert torch.equal(g.outputs["F"], eager), rep
+        plan.grid_map(nodes[::-1].copy(), 0, half // 2)
+        (torch.randn(1 << 18, device="cuda") * 2).sum().item()
+        torch.cuda.synchronize()

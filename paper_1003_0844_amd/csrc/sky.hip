@@ -5,7 +5,8 @@
 //   sky_setup     per sky: n0 components, a/b coefficients, t_b0 = phi_m(0)
 //   sky_prep      per (sky, sample): invert t_b -> t (FP64), interpolate the
 //                 data at t (Sec. VI A), a(t), b(t), Roemer delay; plus the
-//                 detector-grid sums A, B, C of the F combination
+//                 detector-grid sums A, B, C of the F combination; the
+//                 ephemeris of a sample is shared by a group of sky positions
 //   sky_finalize  per sky: fixed-order sum of the A, B, C partials and the
 //                 combination coefficients
 #include "demod.h"
@@ -93,57 +94,147 @@ __device__ __forceinline__ T interp_at(const SegDev& sg, int64_t j, double off) 
   }
 }
 
+// Sky positions per thread of k_sky_prep: the ephemeris at a sample's time is
+// shared by all of them.
+constexpr int SKY_GROUP = 8;
+
+// sin and cos of a small angle (|x| < 0.2) by their Taylor polynomials through
+// x^11 and x^12: remainders below 1e-17 relative.
+__device__ __forceinline__ void small_sincos(double x, double& s, double& c) {
+  const double x2 = x * x;
+  s = x * (1.0 - x2 * (1.0 / 6.0) *
+                     (1.0 - x2 * (1.0 / 20.0) *
+                                (1.0 - x2 * (1.0 / 42.0) * (1.0 - x2 * (1.0 / 72.0) * (1.0 - x2 * (1.0 / 110.0))))));
+  c = 1.0 - x2 * 0.5 *
+                (1.0 - x2 * (1.0 / 12.0) *
+                           (1.0 - x2 * (1.0 / 30.0) *
+                                      (1.0 - x2 * (1.0 / 56.0) *
+                                                 (1.0 - x2 * (1.0 / 90.0) * (1.0 - x2 * (1.0 / 132.0))))));
+}
+
+// The analytic ephemeris at one time t: the angles of ephem_delta as sines and
+// cosines, from which the ephemeris at any nearby time t - d follows by angle
+// addition.
+struct EphemBase {
+  double sm, cm;    // 2 pi (orb_c0 + h/2), h = t orb_rate_c
+  double sh, ch;    // pi h
+  double sth, cth;  // local sidereal angle
+};
+
+__device__ __forceinline__ EphemBase ephem_base(const SegGeo& g, double t) {
+  EphemBase b;
+  const double h = t * g.orb_rate_c;
+  double mid = g.orb_c0 + 0.5 * h;
+  mid -= rint(mid);
+  sincospi(2.0 * mid, &b.sm, &b.cm);
+  sincospi(h, &b.sh, &b.ch);
+  double cs = g.sid_c0 + t * g.sid_rate_c;
+  cs -= rint(cs);
+  sincospi(2.0 * cs, &b.sth, &b.cth);
+  return b;
+}
+
+// dphi_m at t - d and its time derivative (the same quantities as
+// roemer_delta(ephem_delta(t - d))): the orbital angles move by
+// pi orb_rate_c d, the sidereal angle by 2 pi sid_rate_c d.  |d| <= 1000 s
+// (twice the orbit's light time), so both angles stay below 0.08 rad.
+__device__ __forceinline__ void roemer_at(const SegGeo& g, const SkyConst& k, const EphemBase& b, double d,
+                                          double& dpm, double& ddpm) {
+  constexpr double PI = 3.14159265358979323846;
+  const double wo = PI * g.orb_rate_c, ws = 2.0 * PI * g.sid_rate_c;
+  double so, co, ss, cs;
+  small_sincos(wo * d, so, co);
+  small_sincos(ws * d, ss, cs);
+  const double sm = b.sm * co - b.cm * so, cm = b.cm * co + b.sm * so;
+  const double sh = b.sh * co - b.ch * so, ch = b.ch * co + b.sh * so;
+  const double sth = b.sth * cs - b.cth * ss, cth = b.cth * cs + b.sth * ss;
+  const double dxes = -2.0 * g.orb_r * sm * sh, dyes = 2.0 * g.orb_r * cm * sh;
+  const double dxe = g.site_rc * (cth - g.cth0), dye = g.site_rc * (sth - g.sth0);
+  dpm = k.nx * (dxes + dxe) + k.nye * dyes + k.ny * dye;
+  const double vxes = -2.0 * g.orb_r * wo * (cm * sh + sm * ch), vyes = 2.0 * g.orb_r * wo * (cm * ch - sm * sh);
+  const double vxe = -g.site_rc * ws * sth, vye = g.site_rc * ws * cth;
+  ddpm = k.nx * (vxes + vxe) + k.nye * vyes + k.ny * vye;
+}
+
+// Per (sky, sample j): the detector time t of the barycentric grid point
+// t_b0 + j dt, i.e. t = j dt - d with d = dphi_m(t), then x(t) by
+// interpolation, a(t), b(t) and the demodulation record.  d is found from
+// d0 = dphi_m(j dt) by two steps of the fixed-point relation linearised at
+// the current estimate (the derivative is below 1.1e-4 and the curvature below
+// 1e-10 s/s^2, so the first step leaves ~1e-16 s and the second rounding
+// only).  A thread takes one sample for SKY_GROUP sky positions.
 template <typename T, int INTERP>
 __global__ void __launch_bounds__(SKY_BLOCK)
-k_sky_prep(SegDev sg, const SkyConst* __restrict__ skies, Quad<T>* __restrict__ out, int64_t stride,
+k_sky_prep(SegDev sg, const SkyConst* __restrict__ skies, int nsky, Quad<T>* __restrict__ out, int64_t stride,
            double* __restrict__ abc_part) {
   __shared__ double sh[SKY_BLOCK / 64];
-  const int s = blockIdx.y;
-  const SkyConst k = skies[s];
+  const int s0 = blockIdx.y * SKY_GROUP;
+  const int ng = min(SKY_GROUP, nsky - s0);
   const int64_t pos = (int64_t)blockIdx.x * SKY_BLOCK + threadIdx.x;
   const int64_t total = (int64_t)sg.R * sg.Ceff;
+  constexpr double TWO_PI = 6.28318530717958647692;
 
   if (pos < total) {
     const int64_t r = pos / sg.Ceff;
     const int64_t c = pos - r * sg.Ceff;
     const int64_t j = r + (int64_t)sg.R * c;
-    Quad<T> q = {(T)0, (T)0, (T)0, (T)0};
     if (j < sg.n) {
-      EphemD e;
-      double dpm;
-      (void)ssb_to_detector(sg.geo, k, (double)j * sg.dt, e, dpm);
-      const T xr = interp_at<T, INTERP>(sg, j, -dpm / sg.dt);
-      double a, b;
-      amp_ab(k, hour_angle(k, e.cth, e.sth), a, b);
-      double p = sg.f_ref * dpm;
-      p -= rint(p);
-      q.wa = xr * (T)a;
-      q.wb = xr * (T)b;
-      q.p0 = (T)p;
-      q.dd = (T)dpm;
+      const EphemBase b = ephem_base(sg.geo, (double)j * sg.dt);
+      for (int g = 0; g < ng; ++g) {
+        const SkyConst& k = skies[s0 + g];
+        double d, dd, v, dv;
+        roemer_at(sg.geo, k, b, 0.0, d, dd);
+        roemer_at(sg.geo, k, b, d, v, dv);
+        double d2 = (v + dv * d) / (1.0 + dv);
+        roemer_at(sg.geo, k, b, d2, v, dv);
+        const double dpm = (v + dv * d2) / (1.0 + dv);
+        double ss, cs;
+        small_sincos(TWO_PI * sg.geo.sid_rate_c * dpm, ss, cs);
+        const double sth = b.sth * cs - b.cth * ss, cth = b.cth * cs + b.sth * ss;
+        const T xr = interp_at<T, INTERP>(sg, j, -dpm / sg.dt);
+        double a, bb;
+        amp_ab(k, hour_angle(k, cth, sth), a, bb);
+        double p = sg.f_ref * dpm;
+        p -= rint(p);
+        Quad<T> q;
+        q.wa = xr * (T)a;
+        q.wb = xr * (T)bb;
+        q.p0 = (T)p;
+        q.dd = (T)dpm;
+        out[(int64_t)(s0 + g) * stride + pos] = q;
+      }
+    } else {
+      for (int g = 0; g < ng; ++g) out[(int64_t)(s0 + g) * stride + pos] = Quad<T>{(T)0, (T)0, (T)0, (T)0};
     }
-    out[(int64_t)s * stride + pos] = q;
   }
 
   // A, B, C on the detector samples t_i = i dt
-  double aa = 0.0, bb = 0.0, ab = 0.0;
+  double cth = 0.0, sth = 0.0, m = 0.0;
   if (pos < sg.n) {
-    const Ephem e = ephem(sg.geo, (double)pos * sg.dt);
-    double a, b;
-    amp_ab(k, hour_angle(k, e), a, b);
-    const double m = sg.mask ? (sg.mask[pos] ? 1.0 : 0.0) : 1.0;
-    aa = m * a * a;
-    bb = m * b * b;
-    ab = m * a * b;
+    double cs = sg.geo.sid_c0 + (double)pos * sg.dt * sg.geo.sid_rate_c;
+    cs -= rint(cs);
+    sincospi(2.0 * cs, &sth, &cth);
+    m = sg.mask ? (sg.mask[pos] ? 1.0 : 0.0) : 1.0;
   }
-  aa = block_sum<SKY_BLOCK>(aa, sh);
-  bb = block_sum<SKY_BLOCK>(bb, sh);
-  ab = block_sum<SKY_BLOCK>(ab, sh);
-  if (threadIdx.x == 0) {
-    double* p = abc_part + ((int64_t)s * gridDim.x + blockIdx.x) * 3;
-    p[0] = aa;
-    p[1] = bb;
-    p[2] = ab;
+  for (int g = 0; g < ng; ++g) {  // ng is the same for the whole workgroup
+    double aa = 0.0, bb = 0.0, ab = 0.0;
+    if (pos < sg.n) {
+      const SkyConst& k = skies[s0 + g];
+      double a, b;
+      amp_ab(k, hour_angle(k, cth, sth), a, b);
+      aa = m * a * a;
+      bb = m * b * b;
+      ab = m * a * b;
+    }
+    aa = block_sum<SKY_BLOCK>(aa, sh);
+    bb = block_sum<SKY_BLOCK>(bb, sh);
+    ab = block_sum<SKY_BLOCK>(ab, sh);
+    if (threadIdx.x == 0) {
+      double* p = abc_part + ((int64_t)(s0 + g) * gridDim.x + blockIdx.x) * 3;
+      p[0] = aa;
+      p[1] = bb;
+      p[2] = ab;
+    }
   }
 }
 
@@ -206,9 +297,10 @@ int sky_prep_blocks(const SegDev& seg) {
 hipError_t sky_prep(int prec, const SegDev& seg, const SkyConst* d_sky, int nsky, void* d_quads,
                     int64_t stride, double* d_abc_part, int nblk, hipStream_t st) {
   if (nsky <= 0) return hipSuccess;
-  dim3 grid(nblk, nsky), block(SKY_BLOCK);
-#define SKY_CASE(T, I) \
-  hipLaunchKernelGGL((k_sky_prep<T, I>), grid, block, 0, st, seg, d_sky, (Quad<T>*)d_quads, stride, d_abc_part)
+  dim3 grid(nblk, (nsky + SKY_GROUP - 1) / SKY_GROUP), block(SKY_BLOCK);
+#define SKY_CASE(T, I)                                                                                    \
+  hipLaunchKernelGGL((k_sky_prep<T, I>), grid, block, 0, st, seg, d_sky, nsky, (Quad<T>*)d_quads, stride, \
+                     d_abc_part)
   if (prec == 0) {
     if (seg.interp == 0) SKY_CASE(float, 0);
     else if (seg.interp == 1) SKY_CASE(float, 1);

@@ -346,6 +346,7 @@ class Plan:
         self.interp = interp
         self.nseg = len(segments)
         self.dtype = torch.float32 if prec == FP32 else torch.float64
+        self._dt = [float(sg.dt) for sg in segments]
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -473,6 +474,28 @@ class Plan:
         return out
 
     # ---- continuous parameters ----
+    def bin_params(self, nodes: np.ndarray, k, interbin: bool = False):
+        """The continuous parameters of output bins, for eval / refine /
+        amplitudes: nodes[i] and its output index k[i] (the map column plus k_lo,
+        a kmax, or a crossing's k; 2k + h with interbinning, h = 1 for the half
+        bin) give f = (k + bin_offset) / (nfft dt) (band-relative Hz), the
+        node's fdot, alpha, delta.  Returns (params [n, 4] float64, seg [n]
+        int32) on the plan's device."""
+        nodes = np.asarray(nodes, dtype=NODE_DTYPE).reshape(-1)
+        k = np.asarray(k, dtype=np.float64).reshape(-1)
+        if len(k) != len(nodes):
+            raise ValueError("one bin index per node row")
+        kk = k / 2.0 if interbin else k
+        segs = nodes["seg"].astype(np.int64)
+        if len(segs) and (segs.min() < 0 or segs.max() >= self.nseg):
+            raise ValueError("node segment out of range")
+        nfft = np.array([self.info(i)["nfft"] for i in range(self.nseg)], dtype=np.float64)
+        dt = np.array(self._dt, dtype=np.float64)
+        f = (kk + nodes["bin_offset"].astype(np.float64)) / (nfft[segs] * dt[segs])
+        params = np.stack([f, nodes["fdot"], nodes["alpha"], nodes["delta"]], axis=1)
+        return (torch.from_numpy(np.ascontiguousarray(params)).to(self._dev()),
+                torch.from_numpy(segs.astype(np.int32)).to(self._dev()))
+
     def _params(self, params: torch.Tensor, seg: Optional[torch.Tensor]):
         if params.dtype != torch.float64 or params.device != self._dev() or params.dim() != 2 or params.shape[1] != 4:
             raise ValueError("params must be a float64 [n, 4] tensor on cuda:%d" % self.device)

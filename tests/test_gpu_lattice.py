@@ -176,3 +176,42 @@ def test_graph_replays_of_offset_nodes(interbin):
         plan.grid_map(nodes[::-1].copy(), 0, half // 2)
         (torch.randn(1 << 18, device="cuda") * 2).sum().item()
         torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("interbin", [False, True])
+def test_bin_params_reproduce_the_map(interbin):
+    # crossings on lattice nodes -> continuous parameters -> F by the method at
+    # that frequency (fstat_eval, FP64 direct sum): the map value at the bin
+    dt = 13.0
+    sig = one_signal(45, band=1 / (2 * dt), snr=25.0)
+    seg = small_segment(days=1, dt=dt, seed=45, signal=sig)
+    n = int(round(synth.SIDEREAL_DAY / dt))
+    nfft = (1 << int(math.ceil(math.log2(n)))) * (1 if interbin else 2)
+    seg.nfft = nfft
+    spec = fstat.SegmentSpec(x=seg.x, dt=dt, n_days=1, t0=seg.t0, f_ref=seg.f_ref, sigma2=seg.sigma2, nfft=nfft)
+    lat = fstat.Lattice.for_segment(spec, fstat.detector_spec(DET), fstat.ephemeris_spec(EPH))
+    f_sky = seg.f_ref + 1 / (2 * dt)
+    om = 2 * math.pi * f_sky
+    ce, se = math.cos(EPH.obliquity), math.sin(EPH.obliquity)
+    al, de = sig["alpha"], sig["delta"]
+    a1 = om * (math.sin(al) * math.cos(de) * ce + math.sin(de) * se)
+    a2 = om * math.cos(al) * math.cos(de)
+    nodes = lat.nodes(f_sky, sig["fdot"], sig["fdot"], fstat.ephemeris_spec(EPH), sky=(a1, a2, 60.0))
+    banner("lattice bin params", "interbin", interbin, "nodes", len(nodes))
+    plan = make_plan([seg], method.LINEAR_UP2, fstat.FP64)
+    half = nfft // 2 - (1 if interbin else 0)
+    F = plan.grid_map(nodes, 0, half, interbin=interbin).cpu().numpy()
+    thr = float(np.quantile(F, 0.9995))
+    rec, cnt = plan.grid_crossings(nodes, 0, half, thr, 1 << 14, interbin=interbin)
+    got = fstat.Plan.read_crossings(rec, cnt)
+    assert len(got) > 5
+    params, segi = plan.bin_params(nodes[got["node"]], got["k"], interbin=interbin)
+    Fe, _ = plan.eval(params, segi, want_state=False)
+    Fe = Fe.cpu().numpy()
+    if interbin:
+        # integer bins only: the half bins are Eq. (intbin)'s approximation, not F there
+        whole = got["k"] % 2 == 0
+        assert np.any(whole)
+        assert f_error(Fe[whole], got["F"][whole]) < 1e-9
+    else:
+        assert f_error(Fe, got["F"]) < 1e-9

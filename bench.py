@@ -136,6 +136,31 @@ def workload():
     return w, x, nodes
 
 
+def copy_probe_gbps():
+    """The best bandwidth (one read + one write per byte) of the library's
+    streaming copy over a few grid sizes, on 2^30 bytes."""
+    import torch
+    from paper_1003_0844_amd import fstat
+    src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    best, best_blocks = 0.0, 0
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    for blocks in (256, 512, 1024, 2048, 4096, 8192):
+        fstat.copy_probe(dst, src, blocks)
+        torch.cuda.synchronize()
+        ev[0].record()
+        for _ in range(5):
+            fstat.copy_probe(dst, src, blocks)
+        ev[1].record()
+        torch.cuda.synchronize()
+        gbps = 2 * 5 * (1 << 30) / (ev[0].elapsed_time(ev[1]) * 1e-3) / 1e9
+        if gbps > best:
+            best, best_blocks = gbps, blocks
+    del src, dst
+    torch.cuda.empty_cache()
+    return best, best_blocks
+
+
 def lattice_workload(w, x, rule):
     """The full-sky lattice of the segment (Sec. IV, C0 = 3/4) over the uniform
     grid's spindown range, f_sky at the top of the band."""
@@ -284,6 +309,11 @@ def main():
     }
     del F
     torch.cuda.empty_cache()
+    cp, cp_blocks = copy_probe_gbps()
+    out["roofline"]["copy_probe_GBps"] = round(cp, 1)
+    out["roofline"]["path_frac_of_copy"] = round(path_gbs / cp, 4)
+    log("copy probe: %.1f GB/s (%d workgroups); path %.1f GB/s = %.1f %% of it" % (cp, cp_blocks, path_gbs,
+                                                                                 100 * path_gbs / cp))
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(w, x, nodes, args.cpu_seconds, nfft, ib)

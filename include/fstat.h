@@ -399,6 +399,14 @@ fstat_status fstat_profile_read(fstat_plan_t p, int32_t kind, int64_t *launches,
 void fstat_destroy(fstat_plan_t p);
 const char *fstat_strerror(fstat_status s);
 
+/* Measurement aid: copy `bytes` from src to dst (both device, 16-byte aligned,
+ * not overlapping; bytes a multiple of 16) with a grid-stride kernel of
+ * `blocks` workgroups of 256 threads (0: up to 8192) and streaming accesses,
+ * enqueued on hip_stream.  Timing it gives the bandwidth the memory system
+ * sustains for one read and one write of every byte, the reference for the
+ * grid path's own.  FSTAT_EINVAL for bad arguments. */
+fstat_status fstat_copy_probe(void *dst, const void *src, int64_t bytes, int32_t blocks, void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

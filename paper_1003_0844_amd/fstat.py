@@ -97,7 +97,7 @@ CROSSING_DTYPE = np.dtype([("node", "<i8"), ("k", "<i8"), ("F", "<f8")])
 EXPORTS = ("fstat_plan", "fstat_grid", "fstat_graph_create", "fstat_graph_launch", "fstat_graph_destroy",
            "fstat_eval", "fstat_eval_exact", "fstat_refine", "fstat_threshold", "fstat_adjoint", "fstat_amplitudes",
            "fstat_grad", "fstat_plan_info", "fstat_demod_series",
-           "fstat_lattice_fisher", "fstat_lattice_build", "fstat_lattice_nodes",
+           "fstat_lattice_fisher", "fstat_lattice_build", "fstat_lattice_nodes", "fstat_copy_probe",
            "fstat_profile",
            "fstat_profile_read", "fstat_plan_schedule", "fstat_destroy", "fstat_strerror")
 K_SKY, K_PASS1, K_PASS2, K_OTHER = 0, 1, 2, 3
@@ -130,6 +130,7 @@ def lib():
         L.fstat_lattice_fisher.argtypes = [P(_Segment), P(_Detector), P(_Ephemeris), P(ctypes.c_double)]
         L.fstat_lattice_build.argtypes = [P(ctypes.c_double), ctypes.c_double, ctypes.c_double, i32, P(_Lattice)]
         L.fstat_lattice_nodes.argtypes = [P(_Lattice), P(_LatticeRegion), P(_Ephemeris), vp, vp, i64, P(i64)]
+        L.fstat_copy_probe.argtypes = [vp, vp, i64, i32, vp]
         L.fstat_plan_info.argtypes = [vp, i32, P(i64), P(i64), P(ctypes.c_double), P(i32), P(i32)]
         L.fstat_demod_series.argtypes = [vp, vp, vp, vp]
         L.fstat_profile.argtypes = [vp, i32]
@@ -141,7 +142,7 @@ def lib():
         L.fstat_destroy.restype = None
         for name in ("fstat_plan", "fstat_grid", "fstat_graph_create", "fstat_graph_launch", "fstat_amplitudes",
                      "fstat_eval_exact", "fstat_refine", "fstat_threshold", "fstat_lattice_fisher",
-                     "fstat_lattice_build", "fstat_lattice_nodes",
+                     "fstat_lattice_build", "fstat_lattice_nodes", "fstat_copy_probe",
                      "fstat_eval", "fstat_adjoint", "fstat_grad", "fstat_plan_info",
                      "fstat_demod_series", "fstat_profile", "fstat_profile_read", "fstat_plan_schedule"):
             getattr(L, name).restype = i32
@@ -210,6 +211,15 @@ def threshold(alpha: float, n_cells: float) -> float:
     F0 = ctypes.c_double()
     _check(lib().fstat_threshold(float(alpha), float(n_cells), ctypes.byref(F0)), "fstat_threshold")
     return F0.value
+
+
+def copy_probe(dst: torch.Tensor, src: torch.Tensor, blocks: int = 0) -> None:
+    """fstat_copy_probe on the current stream: dst <- src (same byte size)."""
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes or not src.is_cuda or not dst.is_cuda:
+        raise ValueError("src and dst must be device tensors of the same byte size")
+    _check(lib().fstat_copy_probe(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()), nbytes, int(blocks),
+                                  _stream_ptr(src.device.index)), "fstat_copy_probe")
 
 
 def nodes_array(alpha, delta, fdot, seg=0, bin_offset=0.0) -> np.ndarray:

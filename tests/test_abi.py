@@ -105,3 +105,15 @@ def test_node_record_layout_matches_header():
     # fstat_lattice: 2 x 16 + 8 doubles, 2 int32; fstat_lattice_region: 6 doubles, 2 int32
     assert ctypes.sizeof(fstat._Lattice) == 328
     assert ctypes.sizeof(fstat._LatticeRegion) == 56
+
+
+def test_copy_probe_rejects_bad_arguments():
+    # checked before any device work: misaligned, odd sizes, overlap, NULL
+    L = fstat.lib()
+    vp = ctypes.c_void_p
+    assert L.fstat_copy_probe(vp(4096), vp(1 << 20), 0, 0, None) == fstat.EINVAL
+    assert L.fstat_copy_probe(vp(4096), vp(1 << 20), 24, 0, None) == fstat.EINVAL
+    assert L.fstat_copy_probe(vp(4100), vp(1 << 20), 32, 0, None) == fstat.EINVAL
+    assert L.fstat_copy_probe(vp(4096), vp(4096 + 16), 64, 0, None) == fstat.EINVAL
+    assert L.fstat_copy_probe(None, vp(1 << 20), 64, 0, None) == fstat.EINVAL
+    assert L.fstat_copy_probe(vp(4096), vp(1 << 20), 64, -1, None) == fstat.EINVAL

@@ -116,3 +116,13 @@ def test_argument_checks_with_a_plan():
     assert status(lambda: mk(n_days=2)) == fstat.ENOTINTDAYS
     assert status(lambda: mk(mask=np.zeros(len(x), dtype=np.uint8))) == fstat.EINVAL
     assert status(lambda: mk(x=np.r_[x[:-1], np.inf])) == fstat.EINVAL
+
+
+@pytest.mark.parametrize("blocks", [0, 3])
+def test_copy_probe_copies(blocks):
+    banner("copy probe", blocks)
+    src = torch.randn((1 << 22) + 4, device="cuda")
+    dst = torch.zeros_like(src)
+    fstat.copy_probe(dst, src, blocks)
+    torch.cuda.synchronize()
+    assert torch.equal(dst, src)

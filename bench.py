@@ -201,7 +201,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: the F-statistic grid shards over sky positions, "
-              "but this build measures one GPU's share only (--gpus 1).", file=sys.stderr)
+              "and bench.py measures one GPU's share only: run it with --gpus 1.", file=sys.stderr)
         sys.exit(2)
     if args.counters:
         counters_run(args)

@@ -14,7 +14,7 @@ Parameters of the linear model with one spindown are
 xi = (omega_0, omega_1, alpha_1, alpha_2), with the known functions
 m = (t, t^2/2, mu_1(t), mu_2(t)), t the segment time.
 
-Readings of points the paper leaves open (all listed in the design doc):
+Readings of points the paper leaves open:
 
 L-avg    The time average <.> of Eq. (redFm-def) is the mean over the kept
          samples of the segment (gap mask applied), t_j = j dt.  The covariance

@@ -5,7 +5,7 @@ Paper: Sec. III A (Eqs. OS, Fab: the F-statistic), Sec. VI A (Eqs. pham, phas,
 Far, Bt, ia: barycentric resampling; nearest-neighbour and two-step Fourier +
 spline interpolation), Sec. VI B (Eq. DFT).
 
-Readings of points the paper leaves open (all listed in the design doc):
+Readings of points the paper leaves open:
 
 R-norm   Normalisation.  For white noise of per-sample variance sigma^2 the
          one-sided PSD is S0 = 2 sigma^2 dt and the integrals of Eqs. (Fab) are

@@ -2,7 +2,7 @@
 
 Paper: Sec. II ("Response of a detector to a periodic gravitational wave").
 
-Readings where the paper is silent (each is listed in the design doc):
+Readings where the paper is silent:
 
 * The detector's position w.r.t. the SSB comes from an analytic ephemeris: the
   Earth's centre moves on a circle of radius ``orbit_radius`` in the ecliptic

@@ -111,18 +111,20 @@ typedef struct {
   int32_t device;    /* HIP device ordinal */
   int32_t max_batch; /* nodes per FFT batch; 0 = library default (or the tuned value) */
   int32_t autotune;  /* 1: at plan time, time the candidate FFT splits nfft = R x C
-                        (C = 1024, 2048, 4096 columns where valid) and node-batch sizes
-                        (FP32: 32, 64, 128; FP64: 2, 4, 8) of every segment on a sample
-                        grid of 64 sky positions x 16 spindowns and keep the fastest (the
-                        default schedule unless another is at least 3 % faster); one
+                        (C = 1024, 2048, 4096 columns where valid), node-batch sizes
+                        (FP32: 32, 64, 128; FP64: 2, 4, 8) and stream modes (1, 2; see
+                        fstat_plan_schedule) of every segment on a sample grid of 64 sky
+                        positions (FP64: 8) x 16 spindowns, in two sweeps (in order, then
+                        reversed), and keep the fastest (the default schedule unless
+                        another is at least 3 % faster); one
                         tuning per distinct (n, nfft), shared by the segments of that
                         size.  The choice is cached in the file named by the
                         environment variable FSTAT_TUNE_CACHE if it is set.
                         0: fixed defaults. */
 } fstat_options;
-/* Environment: FSTAT_STREAMS=1 at plan creation runs the whole grid pipeline
- * on the caller's stream (no overlap of the two FFT passes of consecutive node
- * batches); meant for per-kernel timing. */
+/* Environment: FSTAT_STREAMS=1 (or 2) at plan creation fixes the stream mode
+ * of every segment (see fstat_plan_schedule) instead of the default or tuned
+ * one; meant for per-kernel timing. */
 
 typedef struct fstat_plan_s *fstat_plan_t;
 
@@ -366,9 +368,13 @@ fstat_status fstat_plan_info(fstat_plan_t p, int32_t seg, int64_t *n, int64_t *n
                              int32_t *fft_R, int32_t *fft_C);
 
 /* The schedule in use for a segment (defaults or autotuned): FFT split
- * nfft = R x C, columns per second-pass workgroup B2, nodes per batch. */
+ * nfft = R x C, columns per second-pass workgroup B2, nodes per batch, and
+ * the stream mode: 1 = both FFT passes of a batch on the caller's stream, one
+ * after the other (the default); 2 = the second pass on a plan-owned side
+ * stream, overlapping the first pass of the next batch.  Host outputs; any
+ * pointer may be NULL. */
 fstat_status fstat_plan_schedule(fstat_plan_t p, int32_t seg, int32_t *R, int32_t *C, int32_t *B2,
-                                 int32_t *batch);
+                                 int32_t *batch, int32_t *streams);
 
 /* Diagnostic: the demodulated, resampled, a/b-weighted series z_a, z_b of one
  * node (the input of the FFTs, natural order), as FP64 device [n][4] =

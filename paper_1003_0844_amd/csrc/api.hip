@@ -21,6 +21,7 @@ struct SegPlan {
   SegDev dev{};
   int B2 = 0;
   int node_cap = 16;  // nodes per FFT batch
+  int streams = 1;    // 1: both FFT passes on the caller's stream; 2: pass 2 on the side stream
   void* twC = nullptr;
   void* twR = nullptr;
   void* twlo = nullptr;
@@ -67,7 +68,7 @@ struct fstat_plan_s {
   hipEvent_t staged = nullptr;
   bool staged_pending = false;
   hipStream_t side = nullptr;  // second stream of the grid pipeline (default priority)
-  bool one_stream = false;
+  int force_streams = 0;  // FSTAT_STREAMS: 1 or 2 for every segment, 0 = per segment
   hipEvent_t ev_p1[2] = {nullptr, nullptr}, ev_p2[2] = {nullptr, nullptr}, ev_sky[2] = {nullptr, nullptr};
   hipEvent_t ev_join = nullptr;
   bool capturing = false;  // a graph capture is recording the launch sequence
@@ -494,11 +495,13 @@ fstat_status launch_grid(fstat_plan_s* p, const GridSched& gs, void* ws, const f
   go.max_xing = out->max_crossings;
   if (out->mode == 2) HIP_TRY(fsk::zero_u64(out->n_crossings, st));
 
-  // Two-stream pipeline: the sky preparation and the first FFT pass run on the
-  // caller's stream, the second pass on the plan's side stream, so that pass 1
-  // of chunk c+1 (arithmetic-bound) overlaps pass 2 of chunk c (memory-bound).
-  // Chunk c uses spill buffer c % 2; sky batch s uses sky set s % 2.
-  hipStream_t s2 = p->one_stream ? st : p->side;
+  // The sky preparation and the first FFT pass run on the caller's stream; the
+  // second pass runs there too (one-stream segments) or on the plan's side
+  // stream (two-stream segments), where pass 1 of chunk c+1 overlaps pass 2 of
+  // chunk c.  Chunk c uses spill buffer c % 2; sky batch s uses sky set s % 2.
+  // Every reuse of a buffer waits for an event recorded on the stream that
+  // last read it, so segments of either kind may follow each other.
+  bool used_side = false;
   const double er = (double)elem_real(prec);
   int64_t chunk = 0;
   int sbi = 0;
@@ -506,6 +509,8 @@ fstat_status launch_grid(fstat_plan_s* p, const GridSched& gs, void* ws, const f
     const SegPlan& sp = p->segs[b.seg];
     const SegDev& d = sp.dev;
     const SkySet& ss = sets[sbi % 2];
+    hipStream_t s2 = sp.streams == 2 ? p->side : st;
+    used_side = used_side || sp.streams == 2;
     const int nblk = fsk::sky_prep_blocks(d);
     const int64_t qstride = (int64_t)d.R * d.Ceff;
     const double rec_bytes = 4.0 * er * (double)qstride;  // one sky record
@@ -541,8 +546,10 @@ fstat_status launch_grid(fstat_plan_s* p, const GridSched& gs, void* ws, const f
     HIP_TRY(hipEventRecord(p->ev_sky[sbi % 2], s2));  // sky set free once its last pass 2 is done
     ++sbi;
   }
-  HIP_TRY(hipEventRecord(p->ev_join, s2));
-  HIP_TRY(hipStreamWaitEvent(st, p->ev_join, 0));
+  if (used_side) {
+    HIP_TRY(hipEventRecord(p->ev_join, p->side));
+    HIP_TRY(hipStreamWaitEvent(st, p->ev_join, 0));
+  }
   return FSTAT_OK;
 }
 
@@ -572,7 +579,7 @@ struct TuneKey {
   int64_t nfft, n;
 };
 
-bool cache_lookup(const TuneKey& k, int& C, int& batch) {
+bool cache_lookup(const TuneKey& k, int& C, int& batch, int& streams) {
   const char* path = std::getenv("FSTAT_TUNE_CACHE");
   if (!path || !*path) return false;
   FILE* f = std::fopen(path, "r");
@@ -580,12 +587,13 @@ bool cache_lookup(const TuneKey& k, int& C, int& batch) {
   char line[256];
   bool found = false;
   while (std::fgets(line, sizeof line, f)) {
-    int pr, ip, c, b;
+    int pr, ip, c, b, ns;
     long long nf, nn;
-    if (std::sscanf(line, "fstat-tune-v2 %d %d %lld %lld %d %d", &pr, &ip, &nf, &nn, &c, &b) == 6 && pr == k.prec &&
-        ip == k.interp && nf == k.nfft && nn == k.n) {
+    if (std::sscanf(line, "fstat-tune-v3 %d %d %lld %lld %d %d %d", &pr, &ip, &nf, &nn, &c, &b, &ns) == 7 &&
+        pr == k.prec && ip == k.interp && nf == k.nfft && nn == k.n) {
       C = c;
       batch = b;
+      streams = ns;
       found = true;  // the last matching line wins
     }
   }
@@ -593,30 +601,35 @@ bool cache_lookup(const TuneKey& k, int& C, int& batch) {
   return found;
 }
 
-void cache_store(const TuneKey& k, int C, int batch) {
+void cache_store(const TuneKey& k, int C, int batch, int streams) {
   const char* path = std::getenv("FSTAT_TUNE_CACHE");
   if (!path || !*path) return;
   FILE* f = std::fopen(path, "a");
   if (!f) return;
-  std::fprintf(f, "fstat-tune-v2 %d %d %lld %lld %d %d\n", k.prec, k.interp, (long long)k.nfft, (long long)k.n, C,
-               batch);
+  std::fprintf(f, "fstat-tune-v3 %d %d %lld %lld %d %d %d\n", k.prec, k.interp, (long long)k.nfft, (long long)k.n,
+               C, batch, streams);
   std::fclose(f);
 }
 
-// Times every valid (C, batch) on an 8-sky x 16-spindown sample of the segment
-// (full map into a scratch buffer; one warm-up and three timed runs each, the
-// fastest counts) and keeps the fastest.  The default schedule is timed first
-// and another one replaces it only when at least 3 % faster, so that timing
-// noise does not pick a schedule that is no better.
+// Times every valid (C, batch, streams) on a 64-sky (FP64: 8-sky) x 16-spindown
+// sample of the segment (full map into a scratch buffer) and keeps the fastest.  After a
+// warm-up, the candidates are timed in two sweeps, in order and then in
+// reverse order, three runs per visit after one untimed run; a candidate's
+// time is its fastest run, so that neither the clock ramp at the start nor
+// drift during the sweep favours a position in the list.  The default
+// schedule (timed first) stays unless the fastest is at least 3 % faster, so
+// that timing noise does not pick a schedule that is no better.
 fstat_status tune_segment(fstat_plan_s* p, int si) {
   SegPlan& sp = p->segs[si];
   const int prec = p->prec;
   const int64_t nfft = sp.dev.nfft;
   const TuneKey key{prec, p->interp, nfft, sp.dev.n};
-  int C = sp.dev.C, batch = sp.node_cap;
-  if (cache_lookup(key, C, batch) && split_valid(prec, nfft, C) && batch > 0) {
+  int C = sp.dev.C, batch = sp.node_cap, streams = sp.streams;
+  if (cache_lookup(key, C, batch, streams) && split_valid(prec, nfft, C) && batch > 0 &&
+      (streams == 1 || streams == 2)) {
     apply_split(sp, prec, C);
     sp.node_cap = batch;
+    sp.streams = p->force_streams ? p->force_streams : streams;
     HIP_TRY(make_split_tables(sp, prec, nullptr));
     HIP_TRY(hipDeviceSynchronize());
     return FSTAT_OK;
@@ -629,7 +642,13 @@ fstat_status tune_segment(fstat_plan_s* p, int si) {
   if (p->max_batch > 0) batches = {p->max_batch};
   else if (prec == 0) batches = {128, 64, 32};
   else batches = {8, 4, 2};
-  const int nsky = 64, nfd = 16;
+  // one stream first (the two passes in turn), then two (pass 2 of a batch
+  // beside pass 1 of the next)
+  std::vector<int> stream_modes;
+  if (p->force_streams) stream_modes = {p->force_streams};
+  else stream_modes = {1, 2};
+  // FP64 runs ~30x slower per node: a smaller sample keeps its tuning short
+  const int nsky = prec == 0 ? 64 : 8, nfd = 16;
   std::vector<fstat_node> nodes(nsky * nfd);
   for (int s = 0; s < nsky; ++s)
     for (int f = 0; f < nfd; ++f) {
@@ -645,8 +664,6 @@ fstat_status tune_segment(fstat_plan_s* p, int si) {
   hipStream_t st = nullptr;
   hipEvent_t ea = nullptr, eb = nullptr;
   fstat_status rc = FSTAT_OK;
-  double best_ms = 1e300;
-  int best_C = sp.dev.C, best_b = sp.node_cap;
   hipError_t e = hipMalloc(&scratch, (size_t)nodes.size() * kh * elem_real(prec));
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipEventCreate(&ea);
@@ -657,31 +674,49 @@ fstat_status tune_segment(fstat_plan_s* p, int si) {
   out.k_lo = 0;
   out.k_hi = kh;
   out.F = scratch;
-  for (size_t ci = 0; rc == FSTAT_OK && ci < cands.size(); ++ci) {
-    apply_split(sp, prec, cands[ci]);
-    if ((e = make_split_tables(sp, prec, st)) != hipSuccess) {
-      rc = from_hip(e);
-      break;
+  struct Cand {
+    int C, batch, streams;
+    double ms;
+  };
+  std::vector<Cand> cs;
+  for (int c : cands)
+    for (int b : batches)
+      for (int ns : stream_modes) cs.push_back(Cand{c, b, ns, 1e300});
+  int cur_C = -1;
+  // one visit: switch to the candidate, one untimed run, then `timed` timed runs
+  auto visit = [&](Cand& c, int timed) -> fstat_status {
+    if (c.C != cur_C) {
+      apply_split(sp, prec, c.C);
+      hipError_t e2 = make_split_tables(sp, prec, st);
+      if (e2 != hipSuccess) return from_hip(e2);
+      cur_C = c.C;
     }
-    for (int b : batches) {
-      sp.node_cap = b;
-      double ms_min = 1e300;
-      for (int rep = 0; rep < 4 && rc == FSTAT_OK; ++rep) {
-        if ((e = hipEventRecord(ea, st)) != hipSuccess) rc = from_hip(e);
-        if (rc == FSTAT_OK) rc = run_grid(p, nodes.data(), (int64_t)nodes.size(), &out, st);
-        if (rc == FSTAT_OK && (e = hipEventRecord(eb, st)) != hipSuccess) rc = from_hip(e);
-        if (rc == FSTAT_OK && (e = hipEventSynchronize(eb)) != hipSuccess) rc = from_hip(e);
-        float ms = 0.f;
-        if (rc == FSTAT_OK && (e = hipEventElapsedTime(&ms, ea, eb)) != hipSuccess) rc = from_hip(e);
-        if (rc == FSTAT_OK && rep > 0) ms_min = std::min(ms_min, (double)ms);  // rep 0 warms up
-      }
-      if (rc == FSTAT_OK && (best_ms == 1e300 || ms_min < 0.97 * best_ms)) {
-        best_ms = ms_min;
-        best_C = cands[ci];
-        best_b = b;
-      }
+    sp.node_cap = c.batch;
+    sp.streams = c.streams;
+    for (int rep = 0; rep <= timed; ++rep) {
+      hipError_t e2 = hipEventRecord(ea, st);
+      if (e2 != hipSuccess) return from_hip(e2);
+      fstat_status r2 = run_grid(p, nodes.data(), (int64_t)nodes.size(), &out, st);
+      if (r2 != FSTAT_OK) return r2;
+      if ((e2 = hipEventRecord(eb, st)) != hipSuccess || (e2 = hipEventSynchronize(eb)) != hipSuccess)
+        return from_hip(e2);
+      float ms = 0.f;
+      if ((e2 = hipEventElapsedTime(&ms, ea, eb)) != hipSuccess) return from_hip(e2);
+      if (rep > 0) c.ms = std::min(c.ms, (double)ms);  // rep 0 warms up
     }
+    return FSTAT_OK;
+  };
+  if (rc == FSTAT_OK) {  // warm-up: clocks up, workspace allocated
+    Cand w = cs[0];
+    rc = visit(w, 3);
   }
+  for (size_t k = 0; rc == FSTAT_OK && k < 2 * cs.size(); ++k)
+    rc = visit(cs[k < cs.size() ? k : 2 * cs.size() - 1 - k], 3);
+  int best = 0;
+  for (size_t k = 1; k < cs.size(); ++k)
+    if (cs[k].ms < cs[best].ms) best = (int)k;
+  if (!(cs[best].ms < 0.97 * cs[0].ms)) best = 0;
+  const int best_C = cs[best].C, best_b = cs[best].batch, best_s = cs[best].streams;
   (void)hipDeviceSynchronize();
   if (scratch) (void)hipFree(scratch);
   if (ea) (void)hipEventDestroy(ea);
@@ -689,10 +724,11 @@ fstat_status tune_segment(fstat_plan_s* p, int si) {
   if (st) (void)hipStreamDestroy(st);
   apply_split(sp, prec, best_C);
   sp.node_cap = best_b;
+  sp.streams = best_s;
   if (rc != FSTAT_OK) return rc;
   HIP_TRY(make_split_tables(sp, prec, nullptr));
   HIP_TRY(hipDeviceSynchronize());
-  cache_store(key, best_C, best_b);
+  cache_store(key, best_C, best_b, best_s);
   return FSTAT_OK;
 }
 
@@ -745,7 +781,12 @@ fstat_status fstat_plan(const fstat_segment* segs, int32_t nseg, const fstat_det
     }
   }
   for (auto& sp : p->segs) sp.node_cap = opt->max_batch > 0 ? opt->max_batch : (opt->prec == 0 ? 16 : 4);
-  if (const char* s1 = std::getenv("FSTAT_STREAMS")) p->one_stream = s1[0] == '1';
+  if (const char* s1 = std::getenv("FSTAT_STREAMS")) {
+    if (s1[0] == '1') p->force_streams = 1;
+    if (s1[0] == '2') p->force_streams = 2;
+  }
+  if (p->force_streams)
+    for (auto& sp : p->segs) sp.streams = p->force_streams;
   hipError_t e = hipEventCreateWithFlags(&p->staged, hipEventDisableTiming);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking);
   for (hipEvent_t* ev : {&p->ev_p1[0], &p->ev_p1[1], &p->ev_p2[0], &p->ev_p2[1], &p->ev_sky[0], &p->ev_sky[1], &p->ev_join})
@@ -764,6 +805,7 @@ fstat_status fstat_plan(const fstat_segment* segs, int32_t nseg, const fstat_det
       if (same >= 0) {
         apply_split(p->segs[i], opt->prec, p->segs[same].dev.C);
         p->segs[i].node_cap = p->segs[same].node_cap;
+        p->segs[i].streams = p->segs[same].streams;
         rc = from_hip(make_split_tables(p->segs[i], opt->prec, nullptr));
       } else {
         rc = tune_segment(p, i);
@@ -791,13 +833,15 @@ fstat_status fstat_plan(const fstat_segment* segs, int32_t nseg, const fstat_det
   return FSTAT_OK;
 }
 
-fstat_status fstat_plan_schedule(fstat_plan_t p, int32_t seg, int32_t* R, int32_t* C, int32_t* B2, int32_t* batch) {
+fstat_status fstat_plan_schedule(fstat_plan_t p, int32_t seg, int32_t* R, int32_t* C, int32_t* B2, int32_t* batch,
+                                 int32_t* streams) {
   if (!p || seg < 0 || seg >= (int32_t)p->segs.size()) return FSTAT_EINVAL;
   const SegPlan& sp = p->segs[seg];
   if (R) *R = sp.dev.R;
   if (C) *C = sp.dev.C;
   if (B2) *B2 = sp.B2;
   if (batch) *batch = sp.node_cap;
+  if (streams) *streams = sp.streams;
   return FSTAT_OK;
 }
 

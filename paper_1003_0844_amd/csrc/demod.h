@@ -24,8 +24,10 @@ __device__ __forceinline__ void sincos_turns(double x, double& s, double& c) {
   sincospi(2.0 * x, &s, &c);
 }
 
-template <typename T>
-__device__ __forceinline__ Pair<T> demod_elem(const Quad<T>& q, double tb0, int64_t j, double dt,
+// J: the sample index type (int inside one FFT pass, where j < nfft <= 2^22,
+// converts to double in one instruction; int64_t elsewhere).
+template <typename T, typename J>
+__device__ __forceinline__ Pair<T> demod_elem(const Quad<T>& q, double tb0, J j, double dt,
                                               double fdot, double fshift) {
   const double dd = (double)q.dd;  // phi_m(t_j) - phi_m(0)
   const double t = (double)j * dt - dd;

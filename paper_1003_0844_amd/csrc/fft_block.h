@@ -241,3 +241,37 @@ __device__ __forceinline__ void block_fft(lds_t<E>* __restrict__ lds,
   fft_fetch<E, L, NCOL, BLOCK>(load, v);
   fft_stage<E, L, NCOL, BLOCK, DIR, 0>(lds, TwTable<typename elem_traits<E>::real, L>{tw}, store, v);
 }
+
+// As block_fft, with each stage-0 input made in two steps: read(i, col)
+// returns what element i of column col needs from memory, make(raw, i, col)
+// turns that into the element.  All reads of a thread are issued before the
+// first element is made, so they are in flight together; a Load functor that
+// reads under a per-element condition keeps each read in its own branch, and
+// the thread then waits for one read after another.
+template <typename E, int L, int NCOL, int BLOCK, int DIR, class Read, class Make, class Store>
+__device__ __forceinline__ void block_fft_split(lds_t<E>* __restrict__ lds,
+                                                const cpx<typename elem_traits<E>::real>* __restrict__ tw,
+                                                Read& read, Make& make, Store& store) {
+  using G = StageShape<L, NCOL, BLOCK, 0>;
+  using Raw = decltype(read(0, 0));
+  const int tid = fft_tid();
+  Raw raw[G::PER][G::Rs];
+#pragma unroll
+  for (int m = 0; m < G::PER; ++m) {
+    const int b = tid + m * BLOCK;
+    if (G::NB % BLOCK == 0 || b < G::NB) {
+#pragma unroll
+      for (int q = 0; q < G::Rs; ++q) raw[m][q] = read(b / NCOL + q * (L / G::Rs), b % NCOL);
+    }
+  }
+  E v[G::PER][G::Rs];
+#pragma unroll
+  for (int m = 0; m < G::PER; ++m) {
+    const int b = tid + m * BLOCK;
+    if (G::NB % BLOCK == 0 || b < G::NB) {
+#pragma unroll
+      for (int q = 0; q < G::Rs; ++q) v[m][q] = make(raw[m][q], b / NCOL + q * (L / G::Rs), b % NCOL);
+    }
+  }
+  fft_stage<E, L, NCOL, BLOCK, DIR, 0>(lds, TwTable<typename elem_traits<E>::real, L>{tw}, store, v);
+}

@@ -134,7 +134,7 @@ def lib():
         L.fstat_plan_info.argtypes = [vp, i32, P(i64), P(i64), P(ctypes.c_double), P(i32), P(i32)]
         L.fstat_demod_series.argtypes = [vp, vp, vp, vp]
         L.fstat_profile.argtypes = [vp, i32]
-        L.fstat_plan_schedule.argtypes = [vp, i32, P(i32), P(i32), P(i32), P(i32)]
+        L.fstat_plan_schedule.argtypes = [vp, i32, P(i32), P(i32), P(i32), P(i32), P(i32)]
         L.fstat_profile_read.argtypes = [vp, i32, P(i64), P(ctypes.c_double), P(ctypes.c_double)]
         L.fstat_destroy.argtypes = [vp]
         L.fstat_strerror.argtypes = [i32]
@@ -377,11 +377,11 @@ class Plan:
         return dict(n=n.value, nfft=nfft.value, sigma2=s2.value, R=R.value, C=C.value)
 
     def schedule(self, seg: int = 0) -> dict:
-        """The FFT split and batch size in use for a segment."""
-        R, C, B2, b = (ctypes.c_int32() for _ in range(4))
+        """The FFT split, batch size and stream mode in use for a segment."""
+        R, C, B2, b, ns = (ctypes.c_int32() for _ in range(5))
         _check(lib().fstat_plan_schedule(self._h, seg, ctypes.byref(R), ctypes.byref(C), ctypes.byref(B2),
-                                         ctypes.byref(b)), "fstat_plan_schedule")
-        return dict(R=R.value, C=C.value, B2=B2.value, batch=b.value)
+                                         ctypes.byref(b), ctypes.byref(ns)), "fstat_plan_schedule")
+        return dict(R=R.value, C=C.value, B2=B2.value, batch=b.value, streams=ns.value)
 
     def profile(self, enable: bool = True):
         """Enable (and reset) or disable per-launch kernel timing."""

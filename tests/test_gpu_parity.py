@@ -243,7 +243,8 @@ def test_autotuned_plan_and_cache(tmp_path, monkeypatch):
                       prec=fstat.FP32, autotune=True)
     sch = plan.schedule()
     assert sch["C"] in (1024, 2048, 4096) and sch["R"] * sch["C"] == w.nfft and sch["batch"] in (32, 64, 128)
-    assert cache.read_text().startswith("fstat-tune-v2")
+    assert sch["streams"] in (1, 2)
+    assert cache.read_text().startswith("fstat-tune-v3")
     nodes = fstat.nodes_array(np.full(3, p["alpha"]), np.full(3, p["delta"]), [p["fdot"], 0.0, -5e-10])
     F = plan.grid_map(nodes, 0, w.nfft // 2).cpu().numpy()
     for i, nd in enumerate(nodes):
@@ -261,7 +262,7 @@ def test_every_split_gives_the_same_map(C, tmp_path, monkeypatch):
     w = synth.TINY
     g, x, sigs = synth.segment_data(w)
     cache = tmp_path / "tune.txt"
-    cache.write_text("fstat-tune-v2 0 %d %d %d %d 8\n" % (w.interp, w.nfft, w.n, C))
+    cache.write_text("fstat-tune-v3 0 %d %d %d %d 8 1\n" % (w.interp, w.nfft, w.n, C))
     monkeypatch.setenv("FSTAT_TUNE_CACHE", str(cache))
     banner("split", C)
     specs = [fstat.SegmentSpec(x=x, dt=w.dt, n_days=w.days, f_ref=synth.F_REF, sigma2=1.0, nfft=w.nfft)]
@@ -274,3 +275,46 @@ def test_every_split_gives_the_same_map(C, tmp_path, monkeypatch):
     for i, nd in enumerate(nodes):
         ref = oracle_map(seg, nd["fdot"], nd["alpha"], nd["delta"], w.interp, np.arange(w.nfft // 2))
         assert f_error(F[i], ref) < PREC_TOL[fstat.FP32]
+
+
+def test_stream_modes_give_identical_maps(tmp_path, monkeypatch):
+    # two segments of different length (the second takes every other sample),
+    # one on one stream and one on two (through the cache file), 20 nodes each
+    # in batches of 8: the map equals, bit for bit, those of plans forced to
+    # one stream and to two streams
+    w = synth.TINY
+    g, x, sigs = synth.segment_data(w)
+    x2 = np.ascontiguousarray(x[::2])
+    n2 = len(x2)
+    cache = tmp_path / "tune.txt"
+    cache.write_text("fstat-tune-v3 0 %d %d %d 4096 8 1\nfstat-tune-v3 0 %d %d %d 2048 8 2\n"
+                     % (w.interp, w.nfft, w.n, w.interp, w.nfft, n2))
+    monkeypatch.setenv("FSTAT_TUNE_CACHE", str(cache))
+    banner("stream modes")
+    specs = [fstat.SegmentSpec(x=x, dt=w.dt, n_days=w.days, f_ref=synth.F_REF, sigma2=1.0, nfft=w.nfft),
+             fstat.SegmentSpec(x=x2, dt=2 * w.dt, n_days=w.days, f_ref=synth.F_REF, sigma2=1.0, nfft=w.nfft)]
+    rng = np.random.default_rng(17)
+    nodes = np.concatenate([fstat.nodes_array(rng.uniform(0, 2 * math.pi, 20), rng.uniform(-1.4, 1.4, 20),
+                                              rng.uniform(-1e-9, 0, 20), seg=s) for s in (0, 1)])
+    maps = {}
+    for force in (None, "1", "2"):
+        if force is None:
+            monkeypatch.delenv("FSTAT_STREAMS", raising=False)
+        else:
+            monkeypatch.setenv("FSTAT_STREAMS", force)
+        plan = fstat.Plan(specs, fstat.detector_spec(DET), fstat.ephemeris_spec(EPH), interp=w.interp,
+                          prec=fstat.FP32, autotune=True)
+        want = (1, 2) if force is None else (int(force), int(force))
+        assert (plan.schedule(0)["streams"], plan.schedule(1)["streams"]) == want
+        assert plan.schedule(0)["batch"] == 8 and plan.schedule(1)["C"] == 2048
+        maps[force] = plan.grid_map(nodes, 0, w.nfft // 2).clone()
+        torch.cuda.synchronize()
+        del plan
+    monkeypatch.delenv("FSTAT_STREAMS", raising=False)
+    assert torch.equal(maps[None], maps["1"]) and torch.equal(maps[None], maps["2"])
+    # and the first segment's rows still match the oracle
+    seg = method.Segment(x=x, dt=w.dt, n_days=w.days, f_ref=synth.F_REF, sigma2=1.0, nfft=w.nfft)
+    for i in (0, 19):
+        nd = nodes[i]
+        ref = oracle_map(seg, nd["fdot"], nd["alpha"], nd["delta"], w.interp, np.arange(w.nfft // 2))
+        assert f_error(maps[None][i].cpu().numpy(), ref) < PREC_TOL[fstat.FP32]

@@ -1,5 +1,5 @@
 """The workloads at their full sizes, in the launch configuration the benchmark
-times (autotuned FP32 plan, two-stream pass pipeline), checked on sampled
+times (autotuned FP32 plan and pass pipeline), checked on sampled
 outputs against the FP64 oracle and by properties that hold at any size.
 
   2-day all-sky grid:  N = 344656, nfft = 2^20, 1024 sky x 16 spindowns + 8 injections

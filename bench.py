@@ -222,11 +222,13 @@ def main():
     half = nfft // 2
     width = 2 * half if ib else half
     log("workload: %s%s; building plan (autotuned)" % (w.name, ", interbinned at nfft %d" % nfft if ib else ""))
+    t_plan = time.perf_counter()
     plan = fstat.Plan([fstat.SegmentSpec(x=x, dt=w.dt, n_days=w.days, nfft=nfft)], fstat.default_detector(),
                       fstat.Ephemeris(), interp=fstat.LINEAR_UP2, prec=fstat.FP32, max_batch=args.max_batch,
                       autotune=True)
     sched = plan.schedule()
-    log("schedule: %s" % sched)
+    log("schedule: %s (plan built in %.2f s, tuning included unless read from FSTAT_TUNE_CACHE)"
+        % (sched, time.perf_counter() - t_plan))
     F = torch.empty((chunk, width), dtype=torch.float32, device="cuda")
 
     def step():

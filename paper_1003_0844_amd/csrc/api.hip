@@ -33,6 +33,7 @@ struct SegPlan {
   double* M = nullptr;
   float* Mf = nullptr;
   uint8_t* mask = nullptr;
+  double* mom = nullptr;  // SegDev::mom
 };
 
 struct ProfPair {
@@ -141,7 +142,7 @@ hipError_t make_split_tables(const SegPlan& sp, int prec, hipStream_t st) {
 }
 
 void free_seg(SegPlan& s) {
-  void* ptrs[] = {s.twC, s.twR, s.twlo, s.twhi, s.x, s.xf, s.y, s.yf, s.M, s.Mf, s.mask};
+  void* ptrs[] = {s.twC, s.twR, s.twlo, s.twhi, s.x, s.xf, s.y, s.yf, s.M, s.Mf, s.mask, s.mom};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   s = SegPlan{};
@@ -240,6 +241,7 @@ fstat_status build_segment(const fstat_segment& s, const fstat_detector& det, co
   double* xraw = nullptr;
   void* work = nullptr;
   double* dvar = nullptr;
+  double* mpart = nullptr;
   fstat_status rc = FSTAT_OK;
   auto fail = [&](hipError_t e) {
     rc = from_hip(e);
@@ -256,6 +258,11 @@ fstat_status build_segment(const fstat_segment& s, const fstat_detector& det, co
       if ((e = hipMemcpy(sp.mask, s.mask, n, hipMemcpyHostToDevice)) != hipSuccess) break;
     }
     if ((e = fsk::prep_mask(xraw, sp.mask, n, sp.x, sp.xf, nullptr)) != hipSuccess) break;
+    // the mask moments that give every sky position's A, B, C
+    d.mask = sp.mask;
+    if ((e = hipMalloc(&sp.mom, 10 * sizeof(double))) != hipSuccess) break;
+    if ((e = hipMalloc(&mpart, (size_t)fsk::mask_moment_blocks(d) * 9 * sizeof(double))) != hipSuccess) break;
+    if ((e = fsk::mask_moments(d, mpart, sp.mom, nullptr)) != hipSuccess) break;
     double sigma2 = s.sigma2;
     if (!(sigma2 > 0.0)) {
       if ((e = hipMalloc(&dvar, sizeof(double))) != hipSuccess) break;
@@ -295,6 +302,7 @@ fstat_status build_segment(const fstat_segment& s, const fstat_detector& det, co
   if (xraw) (void)hipFree(xraw);
   if (work) (void)hipFree(work);
   if (dvar) (void)hipFree(dvar);
+  if (mpart) (void)hipFree(mpart);
   d.x = sp.x;
   d.xf = sp.xf;
   d.y = sp.y;
@@ -302,6 +310,7 @@ fstat_status build_segment(const fstat_segment& s, const fstat_detector& det, co
   d.M = sp.M;
   d.Mf = sp.Mf;
   d.mask = sp.mask;
+  d.mom = sp.mom;
   return rc;
 }
 
@@ -387,7 +396,7 @@ struct GridSched {
   std::vector<double> sky_ad;   // (alpha, delta) per sky of the call
   std::vector<NodeDev> ndev;    // per node, grouped by batch
   std::vector<SkyBatch> batches;
-  size_t max_quads = 0, max_spill = 0, max_part = 0, max_abc = 0;
+  size_t max_quads = 0, max_spill = 0, max_part = 0;
   int max_sky = 0;
   size_t desc_bytes = 0;        // sky list + node list, staged at the start of the workspace
   size_t need_ws = 0;
@@ -439,12 +448,11 @@ void schedule_grid(const fstat_plan_s* p, const fstat_node* nodes, int64_t n_nod
     gs.max_quads = std::max(gs.max_quads, (size_t)bt.nsky * d.R * d.Ceff * 4 * elem_real(prec));
     gs.max_spill = std::max(gs.max_spill, (size_t)sp.node_cap * d.nfft * 4 * elem_real(prec));
     gs.max_part = std::max(gs.max_part, (size_t)sp.node_cap * (d.C / sp.B2) * sizeof(MaxPartial));
-    gs.max_abc = std::max(gs.max_abc, (size_t)bt.nsky * fsk::sky_prep_blocks(d) * 3 * sizeof(double));
     gs.max_sky = std::max(gs.max_sky, bt.nsky);
   }
   gs.desc_bytes = align_up(sky_ad.size() * sizeof(double)) + align_up(ndev.size() * sizeof(NodeDev));
-  const size_t set_bytes = align_up(gs.max_quads) + align_up(gs.max_abc + 8) + align_up(gs.max_sky * sizeof(SkyConst)) +
-                           align_up(gs.max_sky * sizeof(SkyCoef));
+  const size_t set_bytes =
+      align_up(gs.max_quads) + align_up(gs.max_sky * sizeof(SkyConst)) + align_up(gs.max_sky * sizeof(SkyCoef));
   gs.need_ws = gs.desc_bytes + 2 * set_bytes + 2 * align_up(gs.max_spill) + align_up(gs.max_part + 16) + 4096;
 }
 
@@ -460,20 +468,18 @@ void pack_descriptors(const GridSched& gs, char* hp) {
 fstat_status launch_grid(fstat_plan_s* p, const GridSched& gs, void* ws, const fstat_out* out, hipStream_t st) {
   const int prec = p->prec;
   const std::vector<SkyBatch>& batches = gs.batches;
-  const size_t max_quads = gs.max_quads, max_spill = gs.max_spill, max_part = gs.max_part, max_abc = gs.max_abc;
+  const size_t max_quads = gs.max_quads, max_spill = gs.max_spill, max_part = gs.max_part;
   const int max_sky = gs.max_sky;
   Carve cv{(char*)ws};
   double* d_ad = cv.take<double>(gs.sky_ad.size());
   NodeDev* d_nodes = cv.take<NodeDev>(gs.ndev.size());
   struct SkySet {
     void* quads;
-    double* abc;
     SkyConst* sky;
     SkyCoef* coef;
   } sets[2];
   for (auto& ss : sets) {
     ss.quads = cv.take<char>(max_quads);
-    ss.abc = cv.take<double>(max_abc / sizeof(double) + 1);
     ss.sky = cv.take<SkyConst>(max_sky);
     ss.coef = cv.take<SkyCoef>(max_sky);
   }
@@ -511,15 +517,14 @@ fstat_status launch_grid(fstat_plan_s* p, const GridSched& gs, void* ws, const f
     const SkySet& ss = sets[sbi % 2];
     hipStream_t s2 = sp.streams == 2 ? p->side : st;
     used_side = used_side || sp.streams == 2;
-    const int nblk = fsk::sky_prep_blocks(d);
     const int64_t qstride = (int64_t)d.R * d.Ceff;
     const double rec_bytes = 4.0 * er * (double)qstride;  // one sky record
     if (sbi >= 2) HIP_TRY(hipStreamWaitEvent(st, p->ev_sky[sbi % 2], 0));
     HIP_TRY(timed(p, FSTAT_K_OTHER, 0.0, st, [&] { return fsk::sky_setup(d_ad + 2 * b.sky0, b.nsky, d, ss.sky, st); }));
     HIP_TRY(timed(p, FSTAT_K_SKY, rec_bytes * b.nsky, st, [&] {
-      return fsk::sky_prep(prec, d, ss.sky, b.nsky, ss.quads, qstride, ss.abc, nblk, st);
+      return fsk::sky_prep(prec, d, ss.sky, b.nsky, ss.quads, qstride, st);
     }));
-    HIP_TRY(timed(p, FSTAT_K_OTHER, 0.0, st, [&] { return fsk::sky_finalize(d, ss.abc, nblk, b.nsky, ss.coef, st); }));
+    HIP_TRY(timed(p, FSTAT_K_OTHER, 0.0, st, [&] { return fsk::sky_finalize(d, ss.sky, b.nsky, ss.coef, st); }));
     const int node_cap = sp.node_cap;
     for (int n0 = 0; n0 < b.nnode; n0 += node_cap, ++chunk) {
       const int nn = std::min(node_cap, b.nnode - n0);
@@ -1084,10 +1089,8 @@ fstat_status fstat_demod_series(fstat_plan_t p, const fstat_node* node, double* 
   if (!guard.ok) return FSTAT_EDEVICE;
   hipStream_t st = (hipStream_t)hip_stream;
   const SegDev& d = p->segs[node->seg].dev;
-  const int nblk = fsk::sky_prep_blocks(d);
   const size_t qbytes = (size_t)d.R * d.Ceff * 4 * elem_real(p->prec);
-  const size_t need = 256 + align_up(qbytes) + align_up((size_t)nblk * 3 * sizeof(double)) + align_up(sizeof(SkyConst)) +
-                      align_up(sizeof(SkyCoef)) + 1024;
+  const size_t need = 256 + align_up(qbytes) + align_up(sizeof(SkyConst)) + 1024;
   fstat_status rc = ensure_ws(p, need);
   if (rc != FSTAT_OK) return rc;
   rc = ensure_pinned(p, 256);
@@ -1095,7 +1098,6 @@ fstat_status fstat_demod_series(fstat_plan_t p, const fstat_node* node, double* 
   Carve cv{(char*)p->ws};
   double* d_ad = cv.take<double>(2);
   void* d_quads = cv.take<char>(qbytes);
-  double* d_abc = cv.take<double>((size_t)nblk * 3);
   SkyConst* d_sky = cv.take<SkyConst>(1);
   double* hp = (double*)p->pinned;
   hp[0] = node->alpha;
@@ -1105,7 +1107,7 @@ fstat_status fstat_demod_series(fstat_plan_t p, const fstat_node* node, double* 
   p->staged_pending = true;
   const int64_t qstride = (int64_t)d.R * d.Ceff;
   HIP_TRY(fsk::sky_setup(d_ad, 1, d, d_sky, st));
-  HIP_TRY(fsk::sky_prep(p->prec, d, d_sky, 1, d_quads, qstride, d_abc, nblk, st));
+  HIP_TRY(fsk::sky_prep(p->prec, d, d_sky, 1, d_quads, qstride, st));
   return from_hip(fsk::demod_series(p->prec, d, d_sky, d_quads, qstride, node->fdot,
                                     (double)node->bin_offset / (double)d.nfft, out, st));
 }

@@ -48,6 +48,8 @@ struct SegDev {
   const double* M;   // periodic spline second derivatives [2n]
   const float* Mf;
   const uint8_t* mask;  // [n] or null
+  const double* mom;    // [10]: M_k = sum_i m_i e^{i k theta_i}, k = 0..4, (Re, Im); theta_i the
+                        // sidereal angle of detector sample i, m_i its mask value
 };
 
 struct GridOut {
@@ -83,9 +85,12 @@ namespace fsk {
 hipError_t sky_setup(const double* d_alpha_delta, int nsky, const SegDev& seg, SkyConst* d_out, hipStream_t st);
 int sky_prep_blocks(const SegDev& seg);
 hipError_t sky_prep(int prec, const SegDev& seg, const SkyConst* d_sky, int nsky, void* d_quads,
-                    int64_t quad_stride, double* d_abc_part, int nblk_abc, hipStream_t st);
-hipError_t sky_finalize(const SegDev& seg, const double* d_abc_part, int nblk_abc, int nsky, SkyCoef* d_coef,
-                        hipStream_t st);
+                    int64_t quad_stride, hipStream_t st);
+hipError_t sky_finalize(const SegDev& seg, const SkyConst* d_sky, int nsky, SkyCoef* d_coef, hipStream_t st);
+// the segment's mask moments (SegDev::mom) into d_mom[10]; d_part: scratch of
+// mask_moment_blocks(seg) x 9 doubles
+int mask_moment_blocks(const SegDev& seg);
+hipError_t mask_moments(const SegDev& seg, double* d_part, double* d_mom, hipStream_t st);
 hipError_t demod_series(int prec, const SegDev& seg, const SkyConst* d_sky, const void* d_quads,
                         int64_t quad_stride, double fdot, double fshift, double* d_out, hipStream_t st);
 // grid.hip

@@ -4,11 +4,24 @@
 //
 //   sky_setup     per sky: n0 components, a/b coefficients, t_b0 = phi_m(0)
 //   sky_prep      per (sky, sample): invert t_b -> t (FP64), interpolate the
-//                 data at t (Sec. VI A), a(t), b(t), Roemer delay; plus the
-//                 detector-grid sums A, B, C of the F combination; the
+//                 data at t (Sec. VI A), a(t), b(t), Roemer delay; the
 //                 ephemeris of a sample is shared by a group of sky positions
-//   sky_finalize  per sky: fixed-order sum of the A, B, C partials and the
-//                 combination coefficients
+//   sky_finalize  per sky: the detector-grid sums A, B, C of the F combination
+//                 from the segment's mask moments, and the combination
+//                 coefficients
+//   mask_moments  per segment (plan time): M_k = sum_i m_i e^{i k theta_i},
+//                 k = 0..4, theta_i the sidereal angle of detector sample i
+//
+// A, B, C from moments: a and b are trigonometric polynomials of degree 2 in
+// the hour angle H = alpha - theta (Sec. II), so in z = e^{i theta}
+//   a = sum_{h=-2..2} a_h z^h,  a_0 = a0,  a_h = conj(w)^h (c_h + i s_h) / 2,
+//   a_{-h} = conj(a_h),  w = e^{i alpha},
+// with c_h, s_h the cos hH and sin hH coefficients (b alike, b_0 = 0).  The
+// product of two such polynomials f g has coefficients
+// (fg)_k = sum_h f_h g_{k-h}, |k| <= 4, and, both being real,
+//   sum_i m_i f(theta_i) g(theta_i) = (fg)_0 M_0 + 2 Re sum_{k=1..4} (fg)_k M_k.
+// This is the direct sum over the samples rearranged (no approximation); the
+// moments are shared by every sky position of the segment.
 #include "demod.h"
 #include "internal.h"
 
@@ -165,9 +178,8 @@ __device__ __forceinline__ void roemer_at(const SegGeo& g, const SkyConst& k, co
 // only).  A thread takes one sample for SKY_GROUP sky positions.
 template <typename T, int INTERP>
 __global__ void __launch_bounds__(SKY_BLOCK)
-k_sky_prep(SegDev sg, const SkyConst* __restrict__ skies, int nsky, Quad<T>* __restrict__ out, int64_t stride,
-           double* __restrict__ abc_part) {
-  __shared__ double sh[SKY_BLOCK / 64];
+k_sky_prep(SegDev sg, const SkyConst* __restrict__ skies, int nsky, Quad<T>* __restrict__ out,
+           int64_t stride) {
   const int s0 = blockIdx.y * SKY_GROUP;
   const int ng = min(SKY_GROUP, nsky - s0);
   const int64_t pos = (int64_t)blockIdx.x * SKY_BLOCK + threadIdx.x;
@@ -207,62 +219,101 @@ k_sky_prep(SegDev sg, const SkyConst* __restrict__ skies, int nsky, Quad<T>* __r
       for (int g = 0; g < ng; ++g) out[(int64_t)(s0 + g) * stride + pos] = Quad<T>{(T)0, (T)0, (T)0, (T)0};
     }
   }
+}
 
-  // A, B, C on the detector samples t_i = i dt
-  double cth = 0.0, sth = 0.0, m = 0.0;
-  if (pos < sg.n) {
-    double cs = sg.geo.sid_c0 + (double)pos * sg.dt * sg.geo.sid_rate_c;
-    cs -= rint(cs);
-    sincospi(2.0 * cs, &sth, &cth);
-    m = sg.mask ? (sg.mask[pos] ? 1.0 : 0.0) : 1.0;
+// per sky (one thread): A, B, C from the mask moments, then the coefficients
+// of the F combination
+__device__ __forceinline__ cpx<double> cpow_conj(const SkyConst& k, int h) {
+  const cpx<double> w{k.ca, -k.sa};  // conj(e^{i alpha})
+  return h == 1 ? w : cmul(w, w);
+}
+
+// sum_i m_i f(theta_i) g(theta_i) for f, g given by their coefficients in
+// z^h, h = 0..2 (negative h: conjugates)
+__device__ __forceinline__ double moment_sum(const cpx<double> (&f)[3], const cpx<double> (&g)[3],
+                                             const double* __restrict__ mom) {
+  auto coef = [&](const cpx<double> (&c)[3], int h) -> cpx<double> { return h >= 0 ? c[h] : cconj(c[-h]); };
+  double acc = 0.0;
+#pragma unroll
+  for (int kk = 0; kk <= 4; ++kk) {
+    cpx<double> fg{0.0, 0.0};
+#pragma unroll
+    for (int h = -2; h <= 2; ++h) {
+      const int h2 = kk - h;
+      if (h2 < -2 || h2 > 2) continue;
+      fg = cadd(fg, cmul(coef(f, h), coef(g, h2)));
+    }
+    const cpx<double> m{mom[2 * kk], mom[2 * kk + 1]};
+    const double re = fg.x * m.x - fg.y * m.y;  // Re(fg M_k)
+    acc += kk == 0 ? re : 2.0 * re;
   }
-  for (int g = 0; g < ng; ++g) {  // ng is the same for the whole workgroup
-    double aa = 0.0, bb = 0.0, ab = 0.0;
-    if (pos < sg.n) {
-      const SkyConst& k = skies[s0 + g];
-      double a, b;
-      amp_ab(k, hour_angle(k, cth, sth), a, b);
-      aa = m * a * a;
-      bb = m * b * b;
-      ab = m * a * b;
+  return acc;
+}
+
+__global__ void k_sky_finalize(const SkyConst* __restrict__ sky, int nsky, const double* __restrict__ mom,
+                               double sigma2, SkyCoef* __restrict__ coef) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nsky) return;
+  const SkyConst& k = sky[s];
+  const cpx<double> w1 = cpow_conj(k, 1), w2 = cpow_conj(k, 2);
+  const cpx<double> fa[3] = {{k.a0, 0.0}, cmul(w1, cpx<double>{0.5 * k.a1c, 0.5 * k.a1s}),
+                             cmul(w2, cpx<double>{0.5 * k.a2c, 0.5 * k.a2s})};
+  const cpx<double> fb[3] = {{0.0, 0.0}, cmul(w1, cpx<double>{0.5 * k.b1c, 0.5 * k.b1s}),
+                             cmul(w2, cpx<double>{0.5 * k.b2c, 0.5 * k.b2s})};
+  const double A = moment_sum(fa, fa, mom);
+  const double B = moment_sum(fb, fb, mom);
+  const double C = moment_sum(fa, fb, mom);
+  const double D = sigma2 * (A * B - C * C);
+  SkyCoef o;
+  o.A = A;
+  o.B = B;
+  o.C = C;
+  o.cB = B / D;
+  o.cA = A / D;
+  o.cC = 2.0 * C / D;
+  coef[s] = o;
+}
+
+constexpr int MOM_BLOCKS_MAX = 256;
+
+// per workgroup: partial moments over a grid-stride share of the samples
+__global__ void __launch_bounds__(SKY_BLOCK) k_mask_moments(SegDev sg, double* __restrict__ part) {
+  __shared__ double sh[SKY_BLOCK / 64];
+  double acc[9];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) acc[q] = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * SKY_BLOCK + threadIdx.x; i < sg.n; i += (int64_t)gridDim.x * SKY_BLOCK) {
+    const double m = sg.mask ? (sg.mask[i] ? 1.0 : 0.0) : 1.0;
+    double cs = sg.geo.sid_c0 + (double)i * sg.dt * sg.geo.sid_rate_c;  // theta_i / 2 pi
+    cs -= rint(cs);
+    acc[0] += m;
+#pragma unroll
+    for (int kk = 1; kk <= 4; ++kk) {
+      double sn, cn;
+      sincospi(2.0 * kk * cs, &sn, &cn);
+      acc[2 * kk - 1] += m * cn;
+      acc[2 * kk] += m * sn;
     }
-    aa = block_sum<SKY_BLOCK>(aa, sh);
-    bb = block_sum<SKY_BLOCK>(bb, sh);
-    ab = block_sum<SKY_BLOCK>(ab, sh);
-    if (threadIdx.x == 0) {
-      double* p = abc_part + ((int64_t)(s0 + g) * gridDim.x + blockIdx.x) * 3;
-      p[0] = aa;
-      p[1] = bb;
-      p[2] = ab;
-    }
+  }
+#pragma unroll
+  for (int q = 0; q < 9; ++q) {
+    const double v = block_sum<SKY_BLOCK>(acc[q], sh);
+    if (threadIdx.x == 0) part[(int64_t)blockIdx.x * 9 + q] = v;
   }
 }
 
-// one workgroup per sky: fixed-order sum of the per-block partials
-__global__ void __launch_bounds__(SKY_BLOCK)
-k_sky_finalize(const double* __restrict__ part, int nblk, double sigma2, SkyCoef* __restrict__ coef) {
-  __shared__ double sh[SKY_BLOCK / 64];
-  const int s = blockIdx.x;
-  const double* p = part + (int64_t)s * nblk * 3;
-  double A = 0.0, B = 0.0, C = 0.0;
-  for (int i = threadIdx.x; i < nblk; i += SKY_BLOCK) {
-    A += p[3 * i];
-    B += p[3 * i + 1];
-    C += p[3 * i + 2];
-  }
-  A = block_sum<SKY_BLOCK>(A, sh);
-  B = block_sum<SKY_BLOCK>(B, sh);
-  C = block_sum<SKY_BLOCK>(C, sh);
-  if (threadIdx.x == 0) {
-    const double D = sigma2 * (A * B - C * C);
-    SkyCoef o;
-    o.A = A;
-    o.B = B;
-    o.C = C;
-    o.cB = B / D;
-    o.cA = A / D;
-    o.cC = 2.0 * C / D;
-    coef[s + threadIdx.x] = o;
+// fixed-order sum of the partials (one thread per moment component)
+__global__ void k_mask_moments_sum(const double* __restrict__ part, int nblk, double* __restrict__ mom) {
+  const int q = threadIdx.x;
+  if (q >= 9) return;
+  double v = 0.0;
+  for (int b = 0; b < nblk; ++b) v += part[(int64_t)b * 9 + q];
+  // layout (Re, Im) per k: M_0 = (v0, 0), M_k = (v_{2k-1}, v_{2k})
+  if (q == 0) {
+    mom[0] = v;
+    mom[1] = 0.0;
+  } else {
+    mom[q + 1] = v;
   }
 }
 
@@ -295,12 +346,11 @@ int sky_prep_blocks(const SegDev& seg) {
 }
 
 hipError_t sky_prep(int prec, const SegDev& seg, const SkyConst* d_sky, int nsky, void* d_quads,
-                    int64_t stride, double* d_abc_part, int nblk, hipStream_t st) {
+                    int64_t stride, hipStream_t st) {
   if (nsky <= 0) return hipSuccess;
-  dim3 grid(nblk, (nsky + SKY_GROUP - 1) / SKY_GROUP), block(SKY_BLOCK);
-#define SKY_CASE(T, I)                                                                                    \
-  hipLaunchKernelGGL((k_sky_prep<T, I>), grid, block, 0, st, seg, d_sky, nsky, (Quad<T>*)d_quads, stride, \
-                     d_abc_part)
+  dim3 grid(sky_prep_blocks(seg), (nsky + SKY_GROUP - 1) / SKY_GROUP), block(SKY_BLOCK);
+#define SKY_CASE(T, I) \
+  hipLaunchKernelGGL((k_sky_prep<T, I>), grid, block, 0, st, seg, d_sky, nsky, (Quad<T>*)d_quads, stride)
   if (prec == 0) {
     if (seg.interp == 0) SKY_CASE(float, 0);
     else if (seg.interp == 1) SKY_CASE(float, 1);
@@ -314,10 +364,22 @@ hipError_t sky_prep(int prec, const SegDev& seg, const SkyConst* d_sky, int nsky
   return hipGetLastError();
 }
 
-hipError_t sky_finalize(const SegDev& seg, const double* d_part, int nblk, int nsky, SkyCoef* d_coef,
-                        hipStream_t st) {
+hipError_t sky_finalize(const SegDev& seg, const SkyConst* d_sky, int nsky, SkyCoef* d_coef, hipStream_t st) {
   if (nsky <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_sky_finalize, dim3(nsky), dim3(SKY_BLOCK), 0, st, d_part, nblk, seg.sigma2, d_coef);
+  hipLaunchKernelGGL(k_sky_finalize, dim3((nsky + 63) / 64), dim3(64), 0, st, d_sky, nsky, seg.mom, seg.sigma2,
+                     d_coef);
+  return hipGetLastError();
+}
+
+int mask_moment_blocks(const SegDev& seg) {
+  const int64_t b = (seg.n + SKY_BLOCK - 1) / SKY_BLOCK;
+  return (int)(b < MOM_BLOCKS_MAX ? b : MOM_BLOCKS_MAX);
+}
+
+hipError_t mask_moments(const SegDev& seg, double* d_part, double* d_mom, hipStream_t st) {
+  const int nblk = mask_moment_blocks(seg);
+  hipLaunchKernelGGL(k_mask_moments, dim3(nblk), dim3(SKY_BLOCK), 0, st, seg, d_part);
+  hipLaunchKernelGGL(k_mask_moments_sum, dim3(1), dim3(64), 0, st, (const double*)d_part, nblk, d_mom);
   return hipGetLastError();
 }
 

@@ -297,22 +297,37 @@ k_pass2_ib(SegDev sg, const Pair<T>* __restrict__ spill, const NodeDev* __restri
   }
 }
 
+// One wave per node: each lane scans a strided share of the node's partials,
+// then the wave reduces.  "Largest F, ties to the lowest bin" is associative
+// and commutative, so the result equals that of a sequential scan.
 template <typename T>
-__global__ void k_max_finalize(const MaxPartial* __restrict__ part, int nparts, const NodeDev* __restrict__ nodes,
-                               int nnodes, T* __restrict__ Fmax, int64_t* __restrict__ kmax) {
-  const int nd = blockIdx.x * blockDim.x + threadIdx.x;
-  if (nd >= nnodes) return;
+__global__ void __launch_bounds__(64) k_max_finalize(const MaxPartial* __restrict__ part, int nparts,
+                                                    const NodeDev* __restrict__ nodes, T* __restrict__ Fmax,
+                                                    int64_t* __restrict__ kmax) {
+  const int nd = blockIdx.x;
+  const MaxPartial* __restrict__ p = part + (int64_t)nd * nparts;
   double best = -1.0;
   int64_t bk = INT64_MAX;
-  for (int i = 0; i < nparts; ++i) {
-    const MaxPartial p = part[(int64_t)nd * nparts + i];
-    if (p.F > best || (p.F == best && p.k < bk)) {
-      best = p.F;
-      bk = p.k;
+  for (int i = threadIdx.x; i < nparts; i += 64) {
+    const MaxPartial q = p[i];
+    if (q.F > best || (q.F == best && q.k < bk)) {
+      best = q.F;
+      bk = q.k;
     }
   }
-  Fmax[nodes[nd].row] = (T)best;
-  kmax[nodes[nd].row] = bk;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const double f2 = __shfl_down(best, o, 64);
+    const int64_t k2 = __shfl_down(bk, o, 64);
+    if (f2 > best || (f2 == best && k2 < bk)) {
+      best = f2;
+      bk = k2;
+    }
+  }
+  if (threadIdx.x == 0) {
+    Fmax[nodes[nd].row] = (T)best;
+    kmax[nodes[nd].row] = bk;
+  }
 }
 
 __global__ void k_zero_u64(unsigned long long* p) {
@@ -391,13 +406,12 @@ hipError_t grid_pass2(int prec, int R, const SegDev& seg, const void* spill, con
 hipError_t max_finalize(const MaxPartial* part, int nparts, const NodeDev* nodes, int nnodes, int prec,
                         const GridOut& out, hipStream_t st) {
   if (nnodes <= 0) return hipSuccess;
-  dim3 grid((nnodes + 63) / 64), block(64);
+  dim3 grid(nnodes), block(64);
   if (prec == 0)
-    hipLaunchKernelGGL(k_max_finalize<float>, grid, block, 0, st, part, nparts, nodes, nnodes, (float*)out.Fmax,
-                       out.kmax);
+    hipLaunchKernelGGL(k_max_finalize<float>, grid, block, 0, st, part, nparts, nodes, (float*)out.Fmax, out.kmax);
   else
-    hipLaunchKernelGGL(k_max_finalize<double>, grid, block, 0, st, part, nparts, nodes, nnodes,
-                       (double*)out.Fmax, out.kmax);
+    hipLaunchKernelGGL(k_max_finalize<double>, grid, block, 0, st, part, nparts, nodes, (double*)out.Fmax,
+                       out.kmax);
   return hipGetLastError();
 }
 

@@ -172,10 +172,12 @@ __device__ __forceinline__ void roemer_at(const SegGeo& g, const SkyConst& k, co
 // Per (sky, sample j): the detector time t of the barycentric grid point
 // t_b0 + j dt, i.e. t = j dt - d with d = dphi_m(t), then x(t) by
 // interpolation, a(t), b(t) and the demodulation record.  d is found from
-// d0 = dphi_m(j dt) by two steps of the fixed-point relation linearised at
-// the current estimate (the derivative is below 1.1e-4 and the curvature below
-// 1e-10 s/s^2, so the first step leaves ~1e-16 s and the second rounding
-// only).  A thread takes one sample for SKY_GROUP sky positions.
+// d0 = dphi_m(j dt) by one step of the fixed-point relation linearised at d0:
+// d = (dphi_m(t1) + dphi_m'(t1) d0) / (1 + dphi_m'(t1)), t1 = j dt - d0.  d0
+// is within |dphi_m'| x 500 s ~ 0.05 s of the solution and the curvature of
+// dphi_m is below 1e-10 s/s^2, so the step leaves ~1e-13 s (a phase error of
+// 5e-11 turns at 435 Hz); a second step would change rounding only.  A
+// thread takes one sample for SKY_GROUP sky positions.
 template <typename T, int INTERP>
 __global__ void __launch_bounds__(SKY_BLOCK)
 k_sky_prep(SegDev sg, const SkyConst* __restrict__ skies, int nsky, Quad<T>* __restrict__ out,
@@ -197,9 +199,7 @@ k_sky_prep(SegDev sg, const SkyConst* __restrict__ skies, int nsky, Quad<T>* __r
         double d, dd, v, dv;
         roemer_at(sg.geo, k, b, 0.0, d, dd);
         roemer_at(sg.geo, k, b, d, v, dv);
-        double d2 = (v + dv * d) / (1.0 + dv);
-        roemer_at(sg.geo, k, b, d2, v, dv);
-        const double dpm = (v + dv * d2) / (1.0 + dv);
+        const double dpm = (v + dv * d) / (1.0 + dv);
         double ss, cs;
         small_sincos(TWO_PI * sg.geo.sid_rate_c * dpm, ss, cs);
         const double sth = b.sth * cs - b.cth * ss, cth = b.cth * cs + b.sth * ss;

@@ -351,6 +351,7 @@ class Plan:
                             ctypes.byref(h)), "fstat_plan")
         self._keep = None
         self._h = h
+        self._destroy = L.fstat_destroy
         self.device = device
         self.prec = prec
         self.interp = interp
@@ -359,9 +360,12 @@ class Plan:
         self._dt = [float(sg.dt) for sg in segments]
 
     def __del__(self):
+        # the destroy function was bound at creation: at interpreter exit the
+        # module's globals (lib among them) may already be gone
         h = getattr(self, "_h", None)
-        if h is not None and h.value:
-            lib().fstat_destroy(h)
+        destroy = getattr(self, "_destroy", None)
+        if h is not None and h.value and destroy is not None:
+            destroy(h)
             self._h = None
 
     @property
@@ -584,6 +588,7 @@ class GridGraph:
     def __init__(self, plan: Plan, handle: ctypes.c_void_p, outputs: dict):
         self.plan = plan
         self._h = handle
+        self._destroy = lib().fstat_graph_destroy  # bound now, usable at interpreter exit
         self.outputs = outputs
 
     def launch(self):
@@ -591,7 +596,7 @@ class GridGraph:
 
     def close(self):
         if self._h is not None and self._h.value:
-            lib().fstat_graph_destroy(self._h)
+            self._destroy(self._h)
         self._h = None
 
     def __del__(self):

@@ -7,14 +7,20 @@
 //                                             sum_c x[r + R c] e^{-2 pi i c k2/C} ]
 // Pass 1 (one workgroup per column r of one node): build x_j for the a- and
 //   b-weighted series on the fly from the sky record and the node's spindown,
-//   length-C FFT in LDS, inter-pass twiddle, store Z[r][k2] (a and b
-//   interleaved, 16 B per element in FP32).
+//   length-C FFT in LDS, inter-pass twiddle, store Z (a and b interleaved,
+//   16 B per element in FP32).
 // Pass 2 (one workgroup per block of B2 adjacent k2 of one node): length-R FFT
 //   of each column, keep the bins k < nfft/2 (k1 < R/2), combine
 //   F = (B|S_a|^2 + A|S_b|^2 - 2C Re(S_a S_b*)) / (sigma^2 (AB - C^2)) and write
 //   the map row, the per-node maximum or the threshold crossings.
 // The inter-pass spill Z is the only HBM round trip of a node:
-// 2 x 8 B x nfft written and read in FP32.
+// 2 x 8 B x nfft written and read in FP32.  Where a row of pass 2's column
+// block is shorter than 512 B (B2 elements), Z is stored blocked,
+// Z[k2 / B2][r][k2 % B2], so that pass 2 reads one contiguous R x B2 block
+// per workgroup; otherwise row-major, Z[r][k2].  Measured on the 2-day grid:
+// with 256 B rows (nfft = 2^20, B2 = 16) the blocked layout makes pass 2
+// 13 % faster and pass 1 6 % slower (step +3.5 %); with 512 B rows (nfft =
+// 2^19, B2 = 32) pass 2 gains 1 % and pass 1 loses 3 %.
 #include "demod.h"
 #include "fft_block.h"
 #include "internal.h"
@@ -27,6 +33,19 @@ constexpr int cfg_B2(int R) {
 }
 constexpr int cfg_block(int nb) { return nb < 64 ? 64 : (nb > 256 ? 256 : nb); }
 
+// The spill layout for pass 2 blocks of B2 columns (see above).
+template <typename T>
+constexpr bool spill_blocked(int B2) {
+  return B2 * (int)sizeof(Pair<T>) < 512;
+}
+
+// Position of spill element (r, k2) within a node's nfft elements in the
+// blocked layout; lb2 = log2(B2).  A bijection onto [0, R C) when B2 divides C.
+__device__ __forceinline__ int64_t spill_index(int r, int k2, int R, int lb2) {
+  const int B2 = 1 << lb2;
+  return ((int64_t)(k2 >> lb2) * R + r) * B2 + (k2 & (B2 - 1));
+}
+
 // Map the hardware workgroup id so that consecutive logical column blocks run
 // on the same XCD (the dispatcher deals workgroups round-robin over 8 XCDs):
 // adjacent blocks then share L2 lines of the output rows.
@@ -35,7 +54,7 @@ __device__ __forceinline__ int xcd_local(int bid, int nblk) {
   return (bid % 8) * (nblk / 8) + bid / 8;
 }
 
-template <typename T, int C>
+template <typename T, int C, bool BLK>
 __global__ void __launch_bounds__(cfg_block(C / 16))
 k_pass1(SegDev sg, const Quad<T>* __restrict__ quads, int64_t qstride, const SkyConst* __restrict__ skies,
         const NodeDev* __restrict__ nodes, const cpx<T>* __restrict__ twC, const cpx<T>* __restrict__ twlo,
@@ -57,7 +76,8 @@ k_pass1(SegDev sg, const Quad<T>* __restrict__ quads, int64_t qstride, const Sky
     if (c < ceff) return demod_elem<T>(q, tb0, r + R * c, dt, fdot, fshift);
     return Pair<T>{{(T)0, (T)0}, {(T)0, (T)0}};
   };
-  Pair<T>* __restrict__ dst = spill + (int64_t)nd * sg.nfft + (int64_t)r * C;
+  Pair<T>* __restrict__ dst = spill + (int64_t)nd * sg.nfft;
+  const int lb2 = BLK ? __builtin_ctz(cfg_B2<T>(R)) : 0;  // log2 of pass 2's B2 (BLK = spill_blocked)
   // inter-pass twiddle e^{-2 pi i r k2/nfft} for the outputs k2 = i + q STR of a
   // butterfly: (table value at r i) x (table value at r STR)^q
   auto store = [&](int i, int, auto& v, auto str) {
@@ -69,7 +89,13 @@ k_pass1(SegDev sg, const Quad<T>* __restrict__ quads, int64_t qstride, const Sky
     cpx<T> pw[RS];
     powers<RS>(step, pw);
 #pragma unroll
-    for (int q = 0; q < RS; ++q) store_stream(&dst[i + q * STR], twmul(v[q], cmul(base, pw[q])));
+    for (int q = 0; q < RS; ++q) {
+      const int k2 = i + q * STR;
+      int64_t at;
+      if constexpr (BLK) at = spill_index(r, k2, R, lb2);
+      else at = (int64_t)r * C + k2;
+      store_stream(&dst[at], twmul(v[q], cmul(base, pw[q])));
+    }
   };
   if constexpr (C >= 1024) {
     // all sky-record reads of a thread in flight together (the interbinned
@@ -100,8 +126,14 @@ k_pass2(SegDev sg, const Pair<T>* __restrict__ spill, const NodeDev* __restrict_
   const int cb = xcd_local(blockIdx.x, gridDim.x);
   const NodeDev node = nodes[nd];
   const int C = sg.C;
-  const Pair<T>* __restrict__ src = spill + (int64_t)nd * sg.nfft + (int64_t)cb * B2;
-  auto load = [&](int r, int col) -> Pair<T> { return load_stream(&src[(int64_t)r * C + col]); };
+  // blocked: the workgroup's R x B2 elements are contiguous; row-major: rows
+  // of B2 elements at stride C
+  constexpr bool BLK = spill_blocked<T>(B2);
+  const Pair<T>* __restrict__ src = spill + (int64_t)nd * sg.nfft + (BLK ? (int64_t)cb * R * B2 : (int64_t)cb * B2);
+  auto load = [&](int r, int col) -> Pair<T> {
+    if constexpr (BLK) return load_stream(&src[r * B2 + col]);
+    else return load_stream(&src[(int64_t)r * C + col]);
+  };
   const SkyCoef cf = coef[node.sky];
   const T cB = (T)cf.cB, cA = (T)cf.cA, cC = (T)cf.cC;
   const int64_t klo = out.k_lo, khi = out.k_hi;
@@ -201,10 +233,19 @@ k_pass2_ib(SegDev sg, const Pair<T>* __restrict__ spill, const NodeDev* __restri
   const int k2_0 = cb * B2;
   const bool wrap = k2_0 + B2 == C;
   const int k2_x = wrap ? 0 : k2_0 + B2;
-  const Pair<T>* __restrict__ src = spill + (int64_t)nd * sg.nfft;
+  // the own B2 columns and column k2_x, in the spill layout of this B2;
   // ordinary loads: the extra column is read by the neighbouring workgroup
   // too, and with streaming loads this kernel runs 25-30 % slower (measured)
-  auto load = [&](int r, int col) -> Pair<T> { return src[(int64_t)r * C + (col < B2 ? k2_0 + col : k2_x)]; };
+  constexpr bool BLK = spill_blocked<T>(B2);
+  const Pair<T>* __restrict__ src = spill + (int64_t)nd * sg.nfft;
+  auto load = [&](int r, int col) -> Pair<T> {
+    if constexpr (BLK) {
+      const int k2 = col < B2 ? k2_0 + col : k2_x;
+      return src[((int64_t)(k2 / B2) * R + r) * B2 + (k2 % B2)];
+    } else {
+      return src[(int64_t)r * C + (col < B2 ? k2_0 + col : k2_x)];
+    }
+  };
   Pair<T> fin[GL::PER][GL::Rs];
   auto keep = [&](int, int, auto& v, auto, int m) {
 #pragma unroll
@@ -339,11 +380,17 @@ hipError_t launch_pass1(int C, const SegDev& seg, const void* quads, int64_t qst
                         const NodeDev* nodes, int nnodes, const void* twC, const void* twlo, const void* twhi,
                         void* spill, hipStream_t st) {
   dim3 grid(seg.R, nnodes);
-#define P1(CC)                                                                                              \
-  case CC:                                                                                                  \
-    hipLaunchKernelGGL((k_pass1<T, CC>), grid, dim3(cfg_block(CC / 16)), 0, st, seg, (const Quad<T>*)quads, \
-                       qstride, sky, nodes, (const cpx<T>*)twC, (const cpx<T>*)twlo, (const cpx<T>*)twhi,   \
-                       (Pair<T>*)spill);                                                                    \
+  const bool blk = spill_blocked<T>(cfg_B2<T>(seg.R));  // the layout pass 2 reads
+#define P1(CC)                                                                                                  \
+  case CC:                                                                                                      \
+    if (blk)                                                                                                    \
+      hipLaunchKernelGGL((k_pass1<T, CC, true>), grid, dim3(cfg_block(CC / 16)), 0, st, seg,                    \
+                         (const Quad<T>*)quads, qstride, sky, nodes, (const cpx<T>*)twC, (const cpx<T>*)twlo,   \
+                         (const cpx<T>*)twhi, (Pair<T>*)spill);                                                 \
+    else                                                                                                        \
+      hipLaunchKernelGGL((k_pass1<T, CC, false>), grid, dim3(cfg_block(CC / 16)), 0, st, seg,                   \
+                         (const Quad<T>*)quads, qstride, sky, nodes, (const cpx<T>*)twC, (const cpx<T>*)twlo,   \
+                         (const cpx<T>*)twhi, (Pair<T>*)spill);                                                 \
     break;
   switch (C) {
     P1(64) P1(128) P1(256) P1(512) P1(1024) P1(2048) P1(4096)

@@ -112,7 +112,7 @@ typedef struct {
   int32_t max_batch; /* nodes per FFT batch; 0 = library default (or the tuned value) */
   int32_t autotune;  /* 1: at plan time, time the candidate FFT splits nfft = R x C
                         (C = 1024, 2048, 4096 columns where valid), node-batch sizes
-                        (FP32: 32, 64, 128; FP64: 2, 4, 8) and stream modes (1, 2; see
+                        (FP32: 32, 64, 128, 256; FP64: 2, 4, 8) and stream modes (1, 2; see
                         fstat_plan_schedule) of every segment on a sample grid of 64 sky
                         positions (FP64: 8) x 16 spindowns, in two sweeps (in order, then
                         reversed), and keep the fastest (the default schedule unless

@@ -645,7 +645,7 @@ fstat_status tune_segment(fstat_plan_s* p, int si) {
     if (split_valid(prec, nfft, c) && std::find(cands.begin(), cands.end(), c) == cands.end()) cands.push_back(c);
   std::vector<int> batches;
   if (p->max_batch > 0) batches = {p->max_batch};
-  else if (prec == 0) batches = {128, 64, 32};
+  else if (prec == 0) batches = {256, 128, 64, 32};
   else batches = {8, 4, 2};
   // one stream first (the two passes in turn), then two (pass 2 of a batch
   // beside pass 1 of the next)

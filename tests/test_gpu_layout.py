@@ -3,7 +3,8 @@ block (B2 elements) is shorter than 512 B the spill is stored blocked,
 Z[k2 / B2][r][k2 % B2], otherwise row-major, Z[r][k2].  Splits of nfft = 2^16
 are forced through the tuning cache so that both layouts run at a size the
 oracle maps in full: plain maps and interbinned maps (Eq. intbin) against the
-oracle, at both precisions."""
+oracle, at both precisions, and the per-node maxima and threshold crossings of
+the same calls against the map."""
 import numpy as np
 import pytest
 
@@ -63,3 +64,17 @@ def test_spill_layouts_against_oracle(prec, C, interbin, tmp_path, monkeypatch):
             ref = oracle_map(seg, nd["fdot"], nd["alpha"], nd["delta"], w.interp, k)
         err = f_error(F[i], ref)
         assert err < PREC_TOL[prec], (prec, C, interbin, i, err)
+    # the per-node maximum and the threshold crossings read the same spill and
+    # round like the map: their values are the map's, exactly
+    Fmax, kmax = plan.grid_max(nodes, 0, half, interbin=interbin)
+    Fmax, kmax = Fmax.cpu().numpy(), kmax.cpu().numpy()
+    assert np.array_equal(Fmax, F.max(axis=1)) and np.array_equal(kmax, F.argmax(axis=1))
+    # the kernel compares F, widened to FP64, with the FP64 threshold
+    F64 = F.astype(np.float64)
+    thr = float(np.quantile(F64, 0.999))
+    rec, cnt = plan.grid_crossings(nodes, 0, half, thr, 4 * F.size // 1000 + 16, interbin=interbin)
+    got = fstat.Plan.read_crossings(rec, cnt)
+    want = np.argwhere(F64 > thr)
+    assert int(cnt.cpu().item()) == len(want) == len(got)
+    assert sorted(zip(got["node"].tolist(), got["k"].tolist())) == sorted(map(tuple, want.tolist()))
+    assert np.array_equal(np.sort(got["F"]), np.sort(F64[F64 > thr]))

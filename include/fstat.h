@@ -129,9 +129,20 @@ typedef struct {
 typedef struct fstat_plan_s *fstat_plan_t;
 
 /* Create a plan: copies the segments to the device and does the
- * node-independent preparation (gap mask, noise variance, 2x upsampling and
- * spline for the two-step interpolations).  Synchronous.  On success *out
- * receives the plan; release it with fstat_destroy. */
+ * node-independent preparation of Sec. VI A: gap mask, noise variance (the
+ * sigma^2 of the normalisation S0 = 2 sigma^2 dt of Eq. OS for white noise),
+ * and, for the two-step interpolations, the 2x Fourier upsampling of the data
+ * and its spline.  The observation time of every segment must be a whole
+ * number of sidereal days (Sec. III A, the condition under which <ab> = 0 and
+ * F takes the form of Eq. OS): FSTAT_ENOTINTDAYS otherwise.  With
+ * opt->autotune the FFT schedule of every segment size is timed and chosen
+ * (see fstat_options).  Synchronous.  On success *out receives the plan,
+ * which owns device copies of the segments; release it with fstat_destroy.
+ * Errors: FSTAT_EINVAL (NULL pointers, nseg <= 0, options out of range,
+ * non-finite data or geometry, a segment made only of gaps),
+ * FSTAT_EUNSUPPORTED (n < 16, nfft not a power of two in [max(n, 2^10),
+ * 2^22]), FSTAT_ENOMEM, FSTAT_EDEVICE (no device, or opt->device out of
+ * range gives FSTAT_EINVAL). */
 fstat_status fstat_plan(const fstat_segment *segs, int32_t nseg, const fstat_detector *det,
                         const fstat_ephemeris *eph, const fstat_options *opt, fstat_plan_t *out);
 
@@ -331,6 +342,14 @@ typedef struct {
 fstat_status fstat_lattice_build(const double gamma[16], double dp0, double c0, int32_t rule,
                                  fstat_lattice *out);
 
+/* The lattice of one segment: fstat_lattice_fisher over its kept samples, then
+ * fstat_lattice_build with the angular resolution of its Fourier bins,
+ * dp0 = 2 pi / (nfft dt) (nfft = seg->nfft, or the smallest power of two
+ * >= 2n when 0: the plan's FFT length).  Errors as for the two calls, and
+ * FSTAT_EINVAL for an nfft that is not a power of two >= n. */
+fstat_status fstat_lattice_segment(const fstat_segment *seg, const fstat_detector *det, const fstat_ephemeris *eph,
+                                   double c0, int32_t rule, fstat_lattice *out);
+
 /* A sky region and spindown range to cover. */
 typedef struct {
   double f_sky_hz;      /* frequency of the sky mapping, omega_s = 2 pi f_sky (the top of the band:
@@ -359,9 +378,33 @@ fstat_status fstat_lattice_nodes(const fstat_lattice *lat, const fstat_lattice_r
                                  const fstat_ephemeris *eph, fstat_node *nodes, int32_t *coef, int64_t capacity,
                                  int64_t *count);
 
-/* Convenience: F and (if dF != NULL) dF/d(f, fdot, alpha, delta), device [n] and [n][4]. */
+/* F and its gradient for the gradient refinement of candidates off the coarse
+ * grid (the fine search of Sec. VI C, by ascent instead of a simplex): F of
+ * fstat_eval at params and, if dF != NULL, dF/d(f, fdot, alpha, delta) of
+ * fstat_adjoint with unit upstream weights, in one call.
+ *   params: device [n][4] as for fstat_eval; seg: device [n] or NULL
+ *   F: device [n]; dF: device [n][4] or NULL (then F only)
+ * The forward state between the two kernels lives in the plan's workspace
+ * (n x FSTAT_STATE doubles, grown on demand: the call may allocate device
+ * memory, and overlapping calls on one plan race on it).  Invalid segment
+ * indices give NaN.  FSTAT_EINVAL for NULL params/F or n <= 0. */
 fstat_status fstat_grad(fstat_plan_t p, const double *params, const int32_t *seg, int64_t n, double *F,
                         double *dF, void *hip_stream);
+
+/* The continuous parameters of output bins of grid nodes, for fstat_eval,
+ * fstat_grad, fstat_refine and fstat_amplitudes: node i and its output index
+ * k[i] (a map column plus k_lo, a kmax, or a crossing's k; with interbin = 1
+ * the interbinned index 2k + h, h = 1 for the half bin k + 1/2 of Eq. intbin)
+ * give the band-relative frequency f = (k + bin_offset) / (nfft dt) of the
+ * node's segment (Eq. DFT: Fourier frequency k / (nfft dt), shifted by the
+ * node's lattice line, Eq. avec), and its fdot, alpha, delta.
+ *   nodes: host [n]; k: host [n], 0 <= k < nfft/2 (interbin: < nfft)
+ *   params: host [n][4] (f, fdot, alpha, delta), written; seg: host [n] or
+ *   NULL, the nodes' segment indices, written.
+ * FSTAT_EINVAL: NULL pointers, n < 0, interbin not 0/1, a node's segment or
+ * bin out of range (nothing is written then). */
+fstat_status fstat_bin_params(fstat_plan_t p, const fstat_node *nodes, const int64_t *k, int64_t n,
+                              int32_t interbin, double *params, int32_t *seg);
 
 /* Plan facts.  Host outputs; any pointer may be NULL. */
 fstat_status fstat_plan_info(fstat_plan_t p, int32_t seg, int64_t *n, int64_t *nfft, double *sigma2,

@@ -441,7 +441,7 @@ void schedule_grid(const fstat_plan_s* p, const fstat_node* nodes, int64_t n_nod
     batches.push_back(b);
   }
   // workspace: descriptors; two sets of sky data (one per sky-batch parity);
-  // two spill buffers (one per node-chunk parity); max partials
+  // two spill buffers and two sets of max partials (one per node-chunk parity)
   for (const auto& bt : batches) {
     const SegPlan& sp = p->segs[bt.seg];
     const SegDev& d = sp.dev;
@@ -453,7 +453,7 @@ void schedule_grid(const fstat_plan_s* p, const fstat_node* nodes, int64_t n_nod
   gs.desc_bytes = align_up(sky_ad.size() * sizeof(double)) + align_up(ndev.size() * sizeof(NodeDev));
   const size_t set_bytes =
       align_up(gs.max_quads) + align_up(gs.max_sky * sizeof(SkyConst)) + align_up(gs.max_sky * sizeof(SkyCoef));
-  gs.need_ws = gs.desc_bytes + 2 * set_bytes + 2 * align_up(gs.max_spill) + align_up(gs.max_part + 16) + 4096;
+  gs.need_ws = gs.desc_bytes + 2 * set_bytes + 2 * align_up(gs.max_spill) + 2 * align_up(gs.max_part + 16) + 4096;
 }
 
 // Copy the call's descriptors (sky list, node list) into host memory laid out
@@ -486,7 +486,9 @@ fstat_status launch_grid(fstat_plan_s* p, const GridSched& gs, void* ws, const f
   void* d_spill[2];
   d_spill[0] = cv.take<char>(max_spill);
   d_spill[1] = cv.take<char>(max_spill);
-  MaxPartial* d_part = cv.take<MaxPartial>(max_part / sizeof(MaxPartial) + 1);
+  MaxPartial* d_part[2];
+  d_part[0] = cv.take<MaxPartial>(max_part / sizeof(MaxPartial) + 1);
+  d_part[1] = cv.take<MaxPartial>(max_part / sizeof(MaxPartial) + 1);
   GridOut go{};
   go.mode = out->mode;
   go.interbin = out->interbin;
@@ -504,9 +506,12 @@ fstat_status launch_grid(fstat_plan_s* p, const GridSched& gs, void* ws, const f
   // The sky preparation and the first FFT pass run on the caller's stream; the
   // second pass runs there too (one-stream segments) or on the plan's side
   // stream (two-stream segments), where pass 1 of chunk c+1 overlaps pass 2 of
-  // chunk c.  Chunk c uses spill buffer c % 2; sky batch s uses sky set s % 2.
-  // Every reuse of a buffer waits for an event recorded on the stream that
-  // last read it, so segments of either kind may follow each other.
+  // chunk c.  Chunk c uses spill buffer and max partials c % 2; sky batch s
+  // uses sky set s % 2.  Chunk c's pass 2 may run beside chunk c+1's (when c
+  // is on the side stream and c+1 on the caller's), so nothing chunk-level is
+  // shared between consecutive chunks; every reuse of a buffer (by chunk c+2,
+  // sky batch s+2) waits for an event recorded on the stream that last read
+  // it, so segments of either kind may follow each other in any order.
   bool used_side = false;
   const double er = (double)elem_real(prec);
   int64_t chunk = 0;
@@ -541,11 +546,11 @@ fstat_status launch_grid(fstat_plan_s* p, const GridSched& gs, void* ws, const f
       HIP_TRY(hipEventRecord(p->ev_p1[chunk % 2], st));
       HIP_TRY(hipStreamWaitEvent(s2, p->ev_p1[chunk % 2], 0));
       HIP_TRY(timed(p, FSTAT_K_PASS2, p2read + outb, s2, [&] {
-        return fsk::grid_pass2(prec, d.R, d, spill, dn, nn, ss.coef, sp.twR, go, d_part, s2);
+        return fsk::grid_pass2(prec, d.R, d, spill, dn, nn, ss.coef, sp.twR, go, d_part[chunk % 2], s2);
       }));
       if (out->mode == 1)
         HIP_TRY(timed(p, FSTAT_K_OTHER, 0.0, s2,
-                      [&] { return fsk::max_finalize(d_part, d.C / sp.B2, dn, nn, prec, go, s2); }));
+                      [&] { return fsk::max_finalize(d_part[chunk % 2], d.C / sp.B2, dn, nn, prec, go, s2); }));
       HIP_TRY(hipEventRecord(p->ev_p2[chunk % 2], s2));
     }
     HIP_TRY(hipEventRecord(p->ev_sky[sbi % 2], s2));  // sky set free once its last pass 2 is done
@@ -1077,6 +1082,30 @@ fstat_status fstat_grad(fstat_plan_t p, const double* params, const int32_t* seg
   double* state = (double*)p->ws;
   HIP_TRY(fsk::grad_forward(p->d_segs, (int)p->segs.size(), seg, params, n, F, state, st));
   return from_hip(fsk::grad_adjoint(p->d_segs, (int)p->segs.size(), seg, params, n, state, nullptr, dF, st));
+}
+
+fstat_status fstat_bin_params(fstat_plan_t p, const fstat_node* nodes, const int64_t* k, int64_t n, int32_t interbin,
+                              double* params, int32_t* seg) {
+  if (!p || n < 0 || (n > 0 && (!nodes || !k || !params)) || (interbin != 0 && interbin != 1)) return FSTAT_EINVAL;
+  const int nseg = (int)p->segs.size();
+  for (int64_t i = 0; i < n; ++i) {
+    const fstat_node& nd = nodes[i];
+    if (nd.seg < 0 || nd.seg >= nseg || !(std::fabs(nd.bin_offset) < 1.0f)) return FSTAT_EINVAL;
+    const int64_t kmax = p->segs[nd.seg].dev.nfft / 2 * (interbin ? 2 : 1);
+    if (k[i] < 0 || k[i] >= kmax) return FSTAT_EINVAL;
+  }
+  for (int64_t i = 0; i < n; ++i) {
+    const fstat_node& nd = nodes[i];
+    const SegDev& d = p->segs[nd.seg].dev;
+    // output index 2k + h of an interbinned call is the bin k + h/2
+    const double bin = interbin ? 0.5 * (double)k[i] : (double)k[i];
+    params[4 * i] = (bin + (double)nd.bin_offset) / ((double)d.nfft * d.dt);
+    params[4 * i + 1] = nd.fdot;
+    params[4 * i + 2] = nd.alpha;
+    params[4 * i + 3] = nd.delta;
+    if (seg) seg[i] = nd.seg;
+  }
+  return FSTAT_OK;
 }
 
 fstat_status fstat_demod_series(fstat_plan_t p, const fstat_node* node, double* out, void* hip_stream) {

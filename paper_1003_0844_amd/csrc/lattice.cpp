@@ -813,4 +813,20 @@ fstat_status fstat_lattice_nodes(const fstat_lattice* lat, const fstat_lattice_r
   return FSTAT_OK;
 }
 
+fstat_status fstat_lattice_segment(const fstat_segment* seg, const fstat_detector* det, const fstat_ephemeris* eph,
+                                   double c0, int32_t rule, fstat_lattice* out) {
+  if (!seg || !det || !eph || !out || seg->n < 2 || !(seg->dt > 0.0) || !std::isfinite(seg->dt)) return FSTAT_EINVAL;
+  int64_t nfft = seg->nfft;
+  if (nfft == 0) {
+    nfft = 1;
+    while (nfft < 2 * seg->n) nfft <<= 1;
+  }
+  if (nfft < seg->n || (nfft & (nfft - 1)) != 0) return FSTAT_EINVAL;
+  double gamma[16];
+  const fstat_status rc = fstat_lattice_fisher(seg, det, eph, gamma);
+  if (rc != FSTAT_OK) return rc;
+  // the angular frequency spacing of the segment's Fourier bins (Eq. DFT)
+  return fstat_lattice_build(gamma, TWO_PI / ((double)nfft * seg->dt), c0, rule, out);
+}
+
 }  // extern "C"

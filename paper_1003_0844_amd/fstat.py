@@ -97,7 +97,8 @@ CROSSING_DTYPE = np.dtype([("node", "<i8"), ("k", "<i8"), ("F", "<f8")])
 EXPORTS = ("fstat_plan", "fstat_grid", "fstat_graph_create", "fstat_graph_launch", "fstat_graph_destroy",
            "fstat_eval", "fstat_eval_exact", "fstat_refine", "fstat_threshold", "fstat_adjoint", "fstat_amplitudes",
            "fstat_grad", "fstat_plan_info", "fstat_demod_series",
-           "fstat_lattice_fisher", "fstat_lattice_build", "fstat_lattice_nodes", "fstat_copy_probe",
+           "fstat_lattice_fisher", "fstat_lattice_build", "fstat_lattice_segment", "fstat_lattice_nodes",
+           "fstat_copy_probe", "fstat_bin_params",
            "fstat_profile",
            "fstat_profile_read", "fstat_plan_schedule", "fstat_destroy", "fstat_strerror")
 K_SKY, K_PASS1, K_PASS2, K_OTHER = 0, 1, 2, 3
@@ -129,6 +130,9 @@ def lib():
         L.fstat_threshold.argtypes = [ctypes.c_double, ctypes.c_double, P(ctypes.c_double)]
         L.fstat_lattice_fisher.argtypes = [P(_Segment), P(_Detector), P(_Ephemeris), P(ctypes.c_double)]
         L.fstat_lattice_build.argtypes = [P(ctypes.c_double), ctypes.c_double, ctypes.c_double, i32, P(_Lattice)]
+        L.fstat_lattice_segment.argtypes = [P(_Segment), P(_Detector), P(_Ephemeris), ctypes.c_double, i32,
+                                            P(_Lattice)]
+        L.fstat_bin_params.argtypes = [vp, vp, vp, i64, i32, vp, vp]
         L.fstat_lattice_nodes.argtypes = [P(_Lattice), P(_LatticeRegion), P(_Ephemeris), vp, vp, i64, P(i64)]
         L.fstat_copy_probe.argtypes = [vp, vp, i64, i32, vp]
         L.fstat_plan_info.argtypes = [vp, i32, P(i64), P(i64), P(ctypes.c_double), P(i32), P(i32)]
@@ -142,7 +146,8 @@ def lib():
         L.fstat_destroy.restype = None
         for name in ("fstat_plan", "fstat_grid", "fstat_graph_create", "fstat_graph_launch", "fstat_amplitudes",
                      "fstat_eval_exact", "fstat_refine", "fstat_threshold", "fstat_lattice_fisher",
-                     "fstat_lattice_build", "fstat_lattice_nodes", "fstat_copy_probe",
+                     "fstat_lattice_build", "fstat_lattice_segment", "fstat_lattice_nodes", "fstat_copy_probe",
+                     "fstat_bin_params",
                      "fstat_eval", "fstat_adjoint", "fstat_grad", "fstat_plan_info",
                      "fstat_demod_series", "fstat_profile", "fstat_profile_read", "fstat_plan_schedule"):
             getattr(L, name).restype = i32
@@ -308,8 +313,14 @@ class Lattice:
                     rule: int = NU_DEEP_HOLES) -> "Lattice":
         """The lattice of one segment: its reduced Fisher matrix and the
         resolution 2 pi / (nfft dt) of its Fourier bins."""
-        nfft = int(seg.nfft) or 1 << int(math.ceil(math.log2(2 * len(seg.x))))
-        return cls.build(lattice_fisher(seg, det, eph), 2 * math.pi / (nfft * seg.dt), c0, rule)
+        keep: list = []
+        s = _segment_struct(seg, keep)
+        d = _Detector(det.lat, det.lon, det.gamma, det.zeta, det.radius)
+        e = _eph_struct(eph)
+        raw = _Lattice()
+        _check(lib().fstat_lattice_segment(ctypes.byref(s), ctypes.byref(d), ctypes.byref(e), float(c0), int(rule),
+                                           ctypes.byref(raw)), "fstat_lattice_segment")
+        return cls(raw)
 
     def nodes(self, f_sky: float, fdot_lo: float, fdot_hi: float, eph: Ephemeris, sky=None, hemisphere: int = 0,
               seg: int = 0, coef: bool = False):
@@ -357,7 +368,6 @@ class Plan:
         self.interp = interp
         self.nseg = len(segments)
         self.dtype = torch.float32 if prec == FP32 else torch.float64
-        self._dt = [float(sg.dt) for sg in segments]
 
     def __del__(self):
         # the destroy function was bound at creation: at interpreter exit the
@@ -495,20 +505,16 @@ class Plan:
         bin) give f = (k + bin_offset) / (nfft dt) (band-relative Hz), the
         node's fdot, alpha, delta.  Returns (params [n, 4] float64, seg [n]
         int32) on the plan's device."""
-        nodes = np.asarray(nodes, dtype=NODE_DTYPE).reshape(-1)
-        k = np.asarray(k, dtype=np.float64).reshape(-1)
+        nodes = np.ascontiguousarray(np.asarray(nodes, dtype=NODE_DTYPE).reshape(-1))
+        k = np.ascontiguousarray(np.asarray(k, dtype=np.int64).reshape(-1))
         if len(k) != len(nodes):
             raise ValueError("one bin index per node row")
-        kk = k / 2.0 if interbin else k
-        segs = nodes["seg"].astype(np.int64)
-        if len(segs) and (segs.min() < 0 or segs.max() >= self.nseg):
-            raise ValueError("node segment out of range")
-        nfft = np.array([self.info(i)["nfft"] for i in range(self.nseg)], dtype=np.float64)
-        dt = np.array(self._dt, dtype=np.float64)
-        f = (kk + nodes["bin_offset"].astype(np.float64)) / (nfft[segs] * dt[segs])
-        params = np.stack([f, nodes["fdot"], nodes["alpha"], nodes["delta"]], axis=1)
-        return (torch.from_numpy(np.ascontiguousarray(params)).to(self._dev()),
-                torch.from_numpy(segs.astype(np.int32)).to(self._dev()))
+        params = np.empty((len(nodes), 4), dtype=np.float64)
+        segs = np.empty(len(nodes), dtype=np.int32)
+        _check(lib().fstat_bin_params(self._h, nodes.ctypes.data_as(ctypes.c_void_p), k.ctypes.data_as(ctypes.c_void_p),
+                                      len(nodes), int(interbin), params.ctypes.data_as(ctypes.c_void_p),
+                                      segs.ctypes.data_as(ctypes.c_void_p)), "fstat_bin_params")
+        return torch.from_numpy(params).to(self._dev()), torch.from_numpy(segs).to(self._dev())
 
     def _params(self, params: torch.Tensor, seg: Optional[torch.Tensor]):
         if params.dtype != torch.float64 or params.device != self._dev() or params.dim() != 2 or params.shape[1] != 4:

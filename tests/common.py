@@ -53,3 +53,25 @@ def rel_err(got, ref):
 
 def deg(x):
     return math.radians(x)
+
+
+def inversion_tolerances(e_amp, h0, cosi):
+    """Bounds on the errors of h0 (relative) and of cos(iota) that follow from
+    an error of at most e_amp in each of the four amplitudes A1..A4, through
+    the inversion z1 = A1 + i A2, z2 = A4 - i A3, m+- = |z1 +- z2| =
+    h0 (1 +- cos iota)^2 / 2, h0 = (m+ + m-)/2 + sqrt(m+ m-), h0 cos iota =
+    (m+ - m-)/2 (Eqs. ampone, h0iota).  |dz1|, |dz2| <= sqrt(2) e_amp, so
+    |dm+-| <= E = 2 sqrt(2) e_amp; the first term of h0 moves by at most E, the
+    square root (increasing in both factors) by at most its change with both
+    factors moved by E the same way; |d(h0 cos iota)| <= E.  The bound grows
+    like 1 / (1 - |cos iota|): near circular polarisation m- is small and its
+    square root is ill-conditioned."""
+    E = 2.0 * math.sqrt(2.0) * e_amp
+    big = h0 * (1.0 + abs(cosi)) ** 2 / 2.0
+    small = h0 * (1.0 - abs(cosi)) ** 2 / 2.0
+    root = math.sqrt(big * small)
+    d_root = max(math.sqrt((big + E) * (small + E)) - root,
+                 root - math.sqrt(max(big - E, 0.0) * max(small - E, 0.0)))
+    d_h0 = E + d_root
+    d_cosi = (E + abs(cosi) * d_h0) / max(h0 - d_h0, 1e-300)
+    return d_h0 / h0, d_cosi

@@ -89,6 +89,10 @@ def test_calls_on_null_plan_are_rejected():
     assert L.fstat_amplitudes(None, None, None, 1, None, None, None) == fstat.EINVAL
     assert L.fstat_graph_create(None, None, 1, None, None) == fstat.EINVAL
     assert L.fstat_graph_launch(None, None) == fstat.EINVAL
+    k = np.zeros(1, dtype=np.int64)
+    params = np.zeros((1, 4))
+    assert L.fstat_bin_params(None, nodes.ctypes.data_as(ctypes.c_void_p), k.ctypes.data_as(ctypes.c_void_p), 1, 0,
+                              params.ctypes.data_as(ctypes.c_void_p), None) == fstat.EINVAL
     L.fstat_graph_destroy(None)
     L.fstat_destroy(None)
 

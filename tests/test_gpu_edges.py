@@ -118,6 +118,36 @@ def test_argument_checks_with_a_plan():
     assert status(lambda: mk(x=np.r_[x[:-1], np.inf])) == fstat.EINVAL
 
 
+def test_bin_params_of_two_segments():
+    # fstat_bin_params: f = (k + bin_offset) / (nfft dt) of the node's own
+    # segment; interbinned indices 2k + h are half bins; out-of-range bins and
+    # segments are rejected
+    s0 = small_segment(days=1, dt=13.0, seed=56, nfft=16384)
+    s1 = small_segment(days=1, dt=26.0, seed=57, nfft=4096)
+    banner("bin params")
+    plan = make_plan([s0, s1], method.LINEAR_UP2, fstat.FP32)
+    nodes = fstat.nodes_array([0.1, 0.2, 0.3], [0.4, -0.5, 0.6], [-1e-10, 0.0, -2e-10], seg=[0, 1, 1],
+                              bin_offset=[0.0, 0.25, -0.375])
+    k = [17, 2047, 0]
+    p, sg = plan.bin_params(nodes, k)
+    p, sg = p.cpu().numpy(), sg.cpu().numpy()
+    want_f = [17 / (16384 * 13.0), (2047 + 0.25) / (4096 * 26.0), -0.375 / (4096 * 26.0)]
+    assert np.allclose(p[:, 0], want_f, rtol=1e-15, atol=0)
+    assert np.array_equal(p[:, 1:], np.stack([nodes["fdot"], nodes["alpha"], nodes["delta"]], axis=1))
+    assert np.array_equal(sg, [0, 1, 1])
+    pi, _ = plan.bin_params(nodes, [35, 4095, 1], interbin=True)
+    want_i = [17.5 / (16384 * 13.0), (2047.5 + 0.25) / (4096 * 26.0), (0.5 - 0.375) / (4096 * 26.0)]
+    assert np.allclose(pi.cpu().numpy()[:, 0], want_i, rtol=1e-15, atol=0)
+    for bad_k, ib in (([17, 2048, 0], False), ([17, 4096, 0], True), ([-1, 0, 0], False)):
+        with pytest.raises(fstat.FStatError) as e:
+            plan.bin_params(nodes, bad_k, interbin=ib)
+        assert e.value.status == fstat.EINVAL
+    bad = nodes.copy()
+    bad["seg"][0] = 2
+    with pytest.raises(fstat.FStatError):
+        plan.bin_params(bad, k)
+
+
 @pytest.mark.parametrize("blocks", [0, 3])
 def test_copy_probe_copies(blocks):
     banner("copy probe", blocks)

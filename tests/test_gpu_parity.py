@@ -277,26 +277,31 @@ def test_every_split_gives_the_same_map(C, tmp_path, monkeypatch):
         assert f_error(F[i], ref) < PREC_TOL[fstat.FP32]
 
 
-def test_stream_modes_give_identical_maps(tmp_path, monkeypatch):
+@pytest.mark.parametrize("order", [(1, 2), (2, 1)])
+def test_stream_modes_give_identical_outputs(order, tmp_path, monkeypatch):
     # two segments of different length (the second takes every other sample),
-    # one on one stream and one on two (through the cache file), 20 nodes each
-    # in batches of 8: the map equals, bit for bit, those of plans forced to
-    # one stream and to two streams
+    # with the stream modes `order` (through the cache file), 20 nodes each in
+    # batches of 8: the map, the per-node maxima and the threshold crossings
+    # equal, bit for bit, those of plans forced to one stream and to two.
+    # Order (2, 1) puts a two-stream segment before a one-stream one: the last
+    # chunk's second pass on the side stream then runs beside the first pass 2
+    # of the next segment on the caller's stream.
     w = synth.TINY
     g, x, sigs = synth.segment_data(w)
     x2 = np.ascontiguousarray(x[::2])
     n2 = len(x2)
     cache = tmp_path / "tune.txt"
-    cache.write_text("fstat-tune-v3 0 %d %d %d 4096 8 1\nfstat-tune-v3 0 %d %d %d 2048 8 2\n"
-                     % (w.interp, w.nfft, w.n, w.interp, w.nfft, n2))
+    cache.write_text("fstat-tune-v3 0 %d %d %d 4096 8 %d\nfstat-tune-v3 0 %d %d %d 2048 8 %d\n"
+                     % (w.interp, w.nfft, w.n, order[0], w.interp, w.nfft, n2, order[1]))
     monkeypatch.setenv("FSTAT_TUNE_CACHE", str(cache))
-    banner("stream modes")
+    banner("stream modes", order)
     specs = [fstat.SegmentSpec(x=x, dt=w.dt, n_days=w.days, f_ref=synth.F_REF, sigma2=1.0, nfft=w.nfft),
              fstat.SegmentSpec(x=x2, dt=2 * w.dt, n_days=w.days, f_ref=synth.F_REF, sigma2=1.0, nfft=w.nfft)]
     rng = np.random.default_rng(17)
     nodes = np.concatenate([fstat.nodes_array(rng.uniform(0, 2 * math.pi, 20), rng.uniform(-1.4, 1.4, 20),
                                               rng.uniform(-1e-9, 0, 20), seg=s) for s in (0, 1)])
-    maps = {}
+    half = w.nfft // 2
+    res = {}
     for force in (None, "1", "2"):
         if force is None:
             monkeypatch.delenv("FSTAT_STREAMS", raising=False)
@@ -304,17 +309,31 @@ def test_stream_modes_give_identical_maps(tmp_path, monkeypatch):
             monkeypatch.setenv("FSTAT_STREAMS", force)
         plan = fstat.Plan(specs, fstat.detector_spec(DET), fstat.ephemeris_spec(EPH), interp=w.interp,
                           prec=fstat.FP32, autotune=True)
-        want = (1, 2) if force is None else (int(force), int(force))
+        want = order if force is None else (int(force), int(force))
         assert (plan.schedule(0)["streams"], plan.schedule(1)["streams"]) == want
         assert plan.schedule(0)["batch"] == 8 and plan.schedule(1)["C"] == 2048
-        maps[force] = plan.grid_map(nodes, 0, w.nfft // 2).clone()
+        F = plan.grid_map(nodes, 0, half).clone()
+        Fmax, kmax = plan.grid_max(nodes, 0, half)
+        rec, cnt = plan.grid_crossings(nodes, 0, half, 7.0, 200000)
         torch.cuda.synchronize()
+        xs = fstat.Plan.read_crossings(rec, cnt)
+        res[force] = (F, Fmax.clone(), kmax.clone(), int(cnt.cpu().item()),
+                      sorted((int(a), int(b), float(c)) for a, b, c in zip(xs["node"], xs["k"], xs["F"])))
         del plan
     monkeypatch.delenv("FSTAT_STREAMS", raising=False)
-    assert torch.equal(maps[None], maps["1"]) and torch.equal(maps[None], maps["2"])
-    # and the first segment's rows still match the oracle
-    seg = method.Segment(x=x, dt=w.dt, n_days=w.days, f_ref=synth.F_REF, sigma2=1.0, nfft=w.nfft)
-    for i in (0, 19):
+    for force in ("1", "2"):
+        a, b = res[None], res[force]
+        assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1]) and torch.equal(a[2], b[2]), force
+        assert a[3] == b[3] and a[4] == b[4], force
+    F, Fmax, kmax, cnt, xs = res[None]
+    Fc = F.cpu().numpy()
+    assert np.array_equal(Fmax.cpu().numpy(), Fc.max(axis=1))
+    assert np.array_equal(kmax.cpu().numpy(), Fc.argmax(axis=1))
+    assert cnt == int(np.sum(Fc > 7.0)) == len(xs)
+    # and rows of both segments still match the oracle
+    segs = [method.Segment(x=x, dt=w.dt, n_days=w.days, f_ref=synth.F_REF, sigma2=1.0, nfft=w.nfft),
+            method.Segment(x=x2, dt=2 * w.dt, n_days=w.days, f_ref=synth.F_REF, sigma2=1.0, nfft=w.nfft)]
+    for i in (0, 19, 20, 39):
         nd = nodes[i]
-        ref = oracle_map(seg, nd["fdot"], nd["alpha"], nd["delta"], w.interp, np.arange(w.nfft // 2))
-        assert f_error(maps[None][i].cpu().numpy(), ref) < PREC_TOL[fstat.FP32]
+        ref = oracle_map(segs[int(nd["seg"])], nd["fdot"], nd["alpha"], nd["delta"], w.interp, np.arange(half))
+        assert f_error(Fc[i], ref) < PREC_TOL[fstat.FP32], i

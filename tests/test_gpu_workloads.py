@@ -3,7 +3,8 @@ times (autotuned FP32 plan and pass pipeline), checked on sampled
 outputs against the FP64 oracle and by properties that hold at any size.
 
   2-day all-sky grid:  N = 344656, nfft = 2^20, 1024 sky x 16 spindowns + 8 injections
-  uneven segments:     256 segments of 1-6 days with 0-10 % gaps, 64 x 8 nodes each, one graph
+  uneven segments:     256 segments of 1-6 days with 0-10 % gaps, 64 x 8 nodes each, one graph;
+                       two nodes per length over their whole band; mixed stream modes
   6-day grid:          N = 1033968, nfft = 2^21, 8192 x 32 nodes + 32 injections, FP32 vs FP64
   refinement:          4096 candidates half a cell from the 1-day injection, 20 ascent steps
 """
@@ -19,6 +20,7 @@ from oracle import method, model
 from paper_1003_0844_amd import fstat, synth
 from tests.common import DET, EPH
 from tests.gpu_common import PREC_TOL, banner, f_error
+from tests.oracle_jobs import full_band_maps
 
 pytestmark = pytest.mark.gpu
 
@@ -81,38 +83,117 @@ def test_grid2d_full_grid_sampled_bins():
             assert 2 * Fr[kk[1:]].max() > 40.0, (r, 2 * Fr[kk[1:]].max())
 
 
-def test_uneven_segments_one_graph():
+def _pinned_cache(path, segs, plan, streams_of):
+    """A tuning cache with the plan's split and batch per segment length and
+    the stream mode streams_of(days)."""
+    lines = []
+    for i, (d, _, x, _) in enumerate(segs):
+        sc = plan.schedule(i)
+        nfft = plan.info(i)["nfft"]
+        lines.append("fstat-tune-v3 0 %d %d %d %d %d %d" % (fstat.LINEAR_UP2, nfft, len(x), sc["C"], sc["batch"],
+                                                          streams_of(d)))
+    path.write_text("\n".join(sorted(set(lines))) + "\n")
+
+
+def _uneven_outputs(plan, nodes, k_hi, picks):
+    """The whole grid's per-node maxima on [0, k_hi) in one graph launch (timed),
+    then, per FFT length, map and maxima of the picked nodes over their own band,
+    each in a graph of its own."""
+    graph = plan.graph_max(nodes, 0, k_hi)
+    _, el = _timed(graph.launch)
+    out = {"Fmax": graph.outputs["Fmax"].clone(), "kmax": graph.outputs["kmax"].clone(), "s": el}
+    graph.close()
+    for nfft, rows in picks.items():
+        sub = nodes[rows]
+        gm = plan.graph_map(sub, 0, nfft // 2)
+        gx = plan.graph_max(sub, 0, nfft // 2)
+        gm.launch()
+        gx.launch()
+        torch.cuda.synchronize()
+        out[nfft] = (gm.outputs["F"].clone(), gx.outputs["Fmax"].clone(), gx.outputs["kmax"].clone())
+        gm.close()
+        gx.close()
+    return out
+
+
+def test_uneven_segments_one_graph(tmp_path, monkeypatch):
     u = synth.UNEVEN
     banner("uneven segments", u.name)
     segs, grids = synth.uneven_segments(u)
     specs = [fstat.SegmentSpec(x=x, dt=u.dt, n_days=d, t0=t0, mask=m) for d, t0, x, m in segs]
-    plan = _plan(specs, fstat.LINEAR_UP2, fstat.FP32)
     nodes = np.concatenate([fstat.nodes_array(a, dl, fd, i) for i, (a, dl, fd) in enumerate(grids)])
+    per_seg = u.n_sky * u.n_fdot
     # bins common to every segment: nfft = nextpow2(2N) of the shortest one
     k_hi = min(1 << int(math.ceil(math.log2(2 * len(x)))) for _, _, x, _ in segs) // 2
-    graph = plan.graph_max(nodes, 0, k_hi)
-    _, el = _timed(graph.launch)
-    print("uneven: %d nodes over %d segments in one graph launch: %.3f s (%.0f nodes/s)"
-          % (len(nodes), len(segs), el, len(nodes) / el), flush=True)
-    Fmax = graph.outputs["Fmax"].cpu().numpy()
-    kmax = graph.outputs["kmax"].cpu().numpy()
-    # one sampled node per segment length
-    picked = {}
-    for i, (d, _, _, _) in enumerate(segs):
-        picked.setdefault(d, i)
+    # two nodes per segment length (from two segments where there are two),
+    # compared over their segment's whole band
     rng = np.random.default_rng(5)
-    for d, si in sorted(picked.items()):
-        days, t0, x, m = segs[si]
-        seg = method.Segment(x=x, dt=u.dt, n_days=days, t0=t0, mask=m, f_ref=synth.F_REF, sigma2=1.0)
-        r = si * u.n_sky * u.n_fdot + int(rng.integers(0, u.n_sky * u.n_fdot))
+    by_len = {}
+    for i, (d, _, _, _) in enumerate(segs):
+        by_len.setdefault(d, []).append(i)
+    picked = []  # (row, days)
+    for d, idx in sorted(by_len.items()):
+        for s in (idx[0], idx[-1]):
+            picked.append((s * per_seg + int(rng.integers(0, per_seg)), d))
+    jobs = []
+    for r, d in picked:
         nd = nodes[r]
-        ref = method.fstat_bins(seg, nd["fdot"], nd["alpha"], nd["delta"], DET, EPH, method.LINEAR_UP2,
-                                k=np.arange(k_hi), dft="fft")
-        # the maximum is unique as a value; its bin must be one where the
-        # oracle is within the tolerance of its own maximum
-        assert abs(Fmax[r] - ref.max()) / max(ref.max(), 1.0) < PREC_TOL[fstat.FP32], (d, Fmax[r], ref.max())
-        assert ref[kmax[r]] >= ref.max() - 2 * PREC_TOL[fstat.FP32] * max(ref.max(), 1.0), d
-    graph.close()
+        days, t0, x, m = segs[int(nd["seg"])]
+        jobs.append((x, m, u.dt, days, t0, synth.F_REF, 0, float(nd["fdot"]), float(nd["alpha"]),
+                     float(nd["delta"]), method.LINEAR_UP2))
+    refs = full_band_maps(jobs)
+    picks = {}
+    for (r, d), ref in zip(picked, refs):
+        picks.setdefault(2 * len(ref), []).append(r)
+
+    # the autotuned plan (the workload's launch configuration), then the same
+    # splits and batches with stream modes alternating by segment length (a
+    # two-stream segment next to a one-stream one wherever the lengths alternate),
+    # then all on one stream: the three give identical outputs
+    cache = tmp_path / "tuned.txt"
+    monkeypatch.setenv("FSTAT_TUNE_CACHE", str(cache))
+    plan = _plan(specs, fstat.LINEAR_UP2, fstat.FP32)
+    res = {"tuned": _uneven_outputs(plan, nodes, k_hi, picks)}
+    print("uneven: %d nodes over %d segments in one graph launch: %.3f s (%.0f nodes/s)"
+          % (len(nodes), len(segs), res["tuned"]["s"], len(nodes) / res["tuned"]["s"]), flush=True)
+    mixed = tmp_path / "mixed.txt"
+    _pinned_cache(mixed, segs, plan, lambda d: 2 if d % 2 else 1)
+    del plan
+    torch.cuda.empty_cache()
+    monkeypatch.setenv("FSTAT_TUNE_CACHE", str(mixed))
+    for name, force in (("mixed", None), ("one", "1")):
+        if force:
+            monkeypatch.setenv("FSTAT_STREAMS", force)
+        plan = _plan(specs, fstat.LINEAR_UP2, fstat.FP32)
+        if name == "mixed":
+            assert {plan.schedule(i)["streams"] for i in range(len(segs))} == {1, 2}
+        res[name] = _uneven_outputs(plan, nodes, k_hi, picks)
+        del plan
+        torch.cuda.empty_cache()
+    monkeypatch.delenv("FSTAT_STREAMS", raising=False)
+    for name in ("mixed", "one"):
+        for key in ["Fmax", "kmax"] + list(picks):
+            a, b = res["tuned"][key], res[name][key]
+            if isinstance(a, tuple):
+                assert all(torch.equal(p, q) for p, q in zip(a, b)), (name, key)
+            else:
+                assert torch.equal(a, b), (name, key)
+
+    out = res["tuned"]
+    Fmax, kmax = out["Fmax"].cpu().numpy(), out["kmax"].cpu().numpy()
+    for (r, d), ref in zip(picked, refs):
+        nfft = 2 * len(ref)
+        j = picks[nfft].index(r)
+        F, Fm, km = (t[j].cpu().numpy() for t in out[nfft])
+        # the whole band against the oracle, maxima exactly those of the map
+        assert f_error(F, ref) < PREC_TOL[fstat.FP32], (d, r, f_error(F, ref))
+        assert Fm == F.max() and km == int(np.argmax(F)), (d, r)
+        # the grid's maximum over the common bins: unique as a value; its bin
+        # must be one where the oracle is within the tolerance of its maximum
+        top = ref[:k_hi].max()
+        assert abs(Fmax[r] - top) / max(top, 1.0) < PREC_TOL[fstat.FP32], (d, r, Fmax[r], top)
+        assert ref[kmax[r]] >= top - 2 * PREC_TOL[fstat.FP32] * max(top, 1.0), (d, r)
+        assert Fmax[r] == F[:k_hi].max(), (d, r)
 
 
 def test_large6d_fp32_against_fp64_and_noise_law():
@@ -202,7 +283,10 @@ def test_refinement_of_4096_candidates():
         Fo, go = method.fstat_continuous(seg, P0[i], DET, EPH, method.LINEAR_UP2, grad=True)
         assert abs(F0[i] - Fo) / max(Fo, 1.0) < 1e-10
         scale = np.max(np.abs(go * cell))
-        assert np.max(np.abs((dF[i] - go) * cell)) < 1e-8 * scale, (i, dF[i], go)
+        gerr = np.max(np.abs((dF[i] - go) * cell)) / scale
+        print("refinement: candidate %d: F rel err %.2e, gradient err %.2e of its largest cell-scaled component"
+              % (i, abs(F0[i] - Fo) / max(Fo, 1.0), gerr), flush=True)
+        assert gerr < 1e-9, (i, dF[i], go)
         # the linear interpolant has a kink every half sample: a step of h moves
         # ~h/(half sample) of the positions across one, an error that shrinks
         # linearly with h (1e-3 cell gives ~0.5 %), hence a small step

@@ -56,7 +56,12 @@ def both():
 
 def test_lattice_numbers_match_oracle(both):
     lat, lo = both
+    # fstat_lattice_segment: the segment's Fisher matrix and the resolution of
+    # its default FFT length nextpow2(2n) = 2^20, the same as the two calls
     assert lat.dp0 == 2 * math.pi / ((1 << 20) * 0.5)
+    spec, _ = _pair()
+    lat2 = fstat.Lattice.build(fstat.lattice_fisher(spec, FDET, FEPH), 2 * math.pi / ((1 << 20) * 0.5), 0.75)
+    assert np.array_equal(lat.basis, lat2.basis) and lat.theta == lat2.theta
     for name in ("mu", "nu", "theta", "R"):
         assert abs(getattr(lat, name) - lo[name]) < 1e-12 * abs(lo[name]), name
     m1, ma = L.margins(lat.gamma, lat.R)

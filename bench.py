@@ -24,9 +24,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, GB/s
+FP64_PEAK_GFLOPS = 78600.0   # MI355X vector FP64
 PROFILES = os.path.join(ROOT, "profiles")
 # sources that compile into the two FFT-pass kernels
 KERNEL_SOURCES = ("grid.hip", "fft_block.h", "cplx.h", "demod.h", "geometry.h", "internal.h")
+# sources of the refinement kernels (F and its adjoint at continuous parameters)
+GRAD_SOURCES = ("grad.hip", "candidate.h", "demod.h", "geometry.h", "internal.h")
 
 
 def parse():
@@ -35,7 +38,10 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--max-batch", type=int, default=0, help="nodes per FFT batch (0 = library default)")
-    ap.add_argument("--plain-nodes", type=int, default=64)
+    ap.add_argument("--plain-nodes", type=int, default=256)
+    ap.add_argument("--plain-repeats", type=int, default=5)
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the other workloads (uneven segments, 6-day grid, refinement)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--interbin", action="store_true",
@@ -121,6 +127,33 @@ def traffic_record(kernel: str, sched: dict, nfft: int, interbin: bool):
     return None
 
 
+def flop_record(kernels: str, n: int):
+    """FP64 floating-point operations per candidate of the refinement kernels
+    from the committed counter summaries (profiles/*flops*.md, lines
+    'record: kernels=... n=... digest=... flop_per_candidate=...'), or None
+    when none matches the current sources of those kernels."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in GRAD_SOURCES:
+        with open(os.path.join(ROOT, "paper_1003_0844_amd", "csrc", name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
+    digest = h.hexdigest()[:16]
+    if not os.path.isdir(PROFILES):
+        return None
+    for name in sorted(os.listdir(PROFILES)):
+        if "flops" not in name:
+            continue
+        with open(os.path.join(PROFILES, name)) as f:
+            for line in f:
+                line = line.strip().strip("`")
+                if not line.startswith("record:"):
+                    continue
+                kv = dict(t.split("=", 1) for t in line[len("record:"):].split() if "=" in t)
+                if kv.get("kernels") == kernels and kv.get("n") == str(n) and kv.get("digest") == digest:
+                    return float(kv["flop_per_candidate"])
+    return None
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -173,28 +206,212 @@ def lattice_workload(w, x, rule):
     return lat, nodes
 
 
-def cpu_baseline(w, x, nodes, budget_s, nfft, ib):
-    """The FP64 oracle (resampling method, FP64 numpy FFT for the DFT step) on
-    the first nodes of the same grid, until the time budget is used."""
-    import numpy as np
+def _oracle_worker(job):
+    """One worker process of the CPU baseline: the oracle on its share of the
+    nodes until the deadline.  Returns (nodes done, seconds)."""
+    x, dt, days, nfft, ib, nodes, budget_s = job
     from oracle import method, model
     from paper_1003_0844_amd import synth
     det, eph = model.default_detector(), model.Ephemeris()
-    seg = method.Segment(x=x, dt=w.dt, n_days=w.days, f_ref=synth.F_REF, sigma2=1.0, nfft=nfft)
+    seg = method.Segment(x=x, dt=dt, n_days=days, f_ref=synth.F_REF, sigma2=1.0, nfft=nfft)
+    fn = method.fstat_bins_interbinned if ib else method.fstat_bins
     t0 = time.perf_counter()
     done = 0
     for nd in nodes:
-        fn = method.fstat_bins_interbinned if ib else method.fstat_bins
         fn(seg, float(nd["fdot"]), float(nd["alpha"]), float(nd["delta"]), det, eph, method.LINEAR_UP2, dft="fft",
            bin_offset=float(nd["bin_offset"]))
         done += 1
         if time.perf_counter() - t0 > budget_s:
             break
-    el = time.perf_counter() - t0
-    return {"value": done / el, "unit": "nodes/s", "cores": 1, "kind": "oracle",
-            "sample": "%d nodes of the same grid (full band, %d %s each), FP64 resampling method with "
-                      "numpy FP64 FFT, one process, %.1f s incl. the segment's 2x upsampling"
-                      % (done, nfft // 2, "bins and half bins" if ib else "bins", el)}
+    return done, time.perf_counter() - t0
+
+
+def cpu_cores() -> int:
+    """Host cores the baseline may use: those this process may run on, at
+    most 16 (the host share of one GPU)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def cpu_baseline(w, x, nodes, budget_s, nfft, ib):
+    """The FP64 oracle (resampling method, FP64 numpy FFT for the DFT step) on
+    nodes of the same grid, one single-threaded worker process per host core,
+    each on its own nodes until the time budget is used; nodes/s = all nodes
+    done over the wall time of the pool."""
+    import multiprocessing as mp
+    cores = cpu_cores()
+    per = max(4, int(budget_s) + 4)    # more nodes than a worker finishes in the budget
+    jobs = [(x, w.dt, w.days, nfft, ib, nodes[c * per:(c + 1) * per], budget_s) for c in range(cores)]
+    env_threads = {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")}
+    for k in env_threads:
+        os.environ[k] = "1"   # one thread per worker (inherited by the spawned processes)
+    try:
+        t0 = time.perf_counter()
+        with mp.get_context("spawn").Pool(cores) as pool:
+            res = pool.map(_oracle_worker, jobs, chunksize=1)
+        wall = time.perf_counter() - t0
+    finally:
+        for k, v in env_threads.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    done = sum(r[0] for r in res)
+    busy = max(r[1] for r in res)
+    return {"value": done / wall, "unit": "nodes/s", "cores": cores, "kind": "oracle",
+            "sample": "%d nodes of the same grid (full band, %d %s each) in %d single-threaded worker processes "
+                      "(one per host core), FP64 resampling method with numpy FP64 FFT; %.1f s wall incl. process "
+                      "start and each worker's 2x upsampling of the segment (%.1f s in the slowest worker's loop)"
+                      % (done, nfft // 2, "bins and half bins" if ib else "bins", cores, wall, busy)}
+
+
+def _median_time(fn, reps):
+    import torch
+    ts = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t)
+    ts.sort()
+    return ts[len(ts) // 2]
+
+
+def _call_bytes(plan, fn):
+    """Algorithmic HBM bytes of one eager grid call, from the library's
+    per-launch accounting (sky records, spill, outputs)."""
+    import torch
+    from paper_1003_0844_amd import fstat
+    plan.profile(True)
+    fn()
+    torch.cuda.synchronize()
+    b = sum(plan.profile_read(k)["bytes"] for k in (fstat.K_SKY, fstat.K_PASS1, fstat.K_PASS2))
+    plan.profile(False)
+    return b
+
+
+def uneven_leg():
+    """256 segments of 1-6 sidereal days with 0-10 % gaps, 64 sky x 8 spindowns
+    each (131072 nodes, nfft 2^19-2^21), per-node maxima over the bins common to
+    all segments, the whole call replayed as one launch of its HIP graph."""
+    import numpy as np
+    import torch
+    from paper_1003_0844_amd import fstat, synth
+    u = synth.UNEVEN
+    t0 = time.perf_counter()
+    segs, grids = synth.uneven_segments(u)
+    specs = [fstat.SegmentSpec(x=x, dt=u.dt, n_days=d, t0=t, mask=m) for d, t, x, m in segs]
+    nodes = np.concatenate([fstat.nodes_array(a, dl, fd, i) for i, (a, dl, fd) in enumerate(grids)])
+    k_hi = min(1 << int(math.ceil(math.log2(2 * len(x)))) for _, _, x, _ in segs) // 2
+    plan = fstat.Plan(specs, fstat.default_detector(), fstat.Ephemeris(), interp=fstat.LINEAR_UP2, prec=fstat.FP32,
+                      autotune=True)
+    log("uneven: data and plan (autotuned) in %.1f s" % (time.perf_counter() - t0))
+    nbytes = _call_bytes(plan, lambda: plan.grid_max(nodes, 0, k_hi))
+    graph = plan.graph_max(nodes, 0, k_hi)
+    graph.launch()
+    s = _median_time(graph.launch, 3)
+    graph.close()
+    scheds = {}
+    for i, (d, _, _, _) in enumerate(segs):
+        scheds.setdefault(str(d), plan.schedule(i))
+    del plan
+    torch.cuda.empty_cache()
+    gbs = nbytes / s / 1e9
+    log("uneven: %.0f nodes/s (%.3f s per launch), %.1f GB/s algorithmic" % (len(nodes) / s, s, gbs))
+    return {"workload": u.name + ", per-node maximum on bins [0, %d), LINEAR_UP2, FP32 with FP64 phase" % k_hi,
+            "launch": "one HIP-graph launch of the whole call (median of 3)",
+            "nodes": int(len(nodes)), "value": round(len(nodes) / s, 1), "unit": "nodes/s", "s_per_call": round(s, 4),
+            "bytes_per_node": round(nbytes / len(nodes)), "path_GBps": round(gbs, 1),
+            "path_frac": round(gbs / HBM_PEAK_GBS, 4), "schedule_by_days": scheds}
+
+
+def large6d_leg():
+    """6 sidereal days (N = 1033968, nfft = 2^21), 8192 sky x 32 spindowns,
+    per-node maximum over the band: FP32 on the whole grid, FP64 (autotuned
+    batches) on its first 8192 nodes, and their per-node maxima compared."""
+    import numpy as np
+    import torch
+    from paper_1003_0844_amd import fstat, synth
+    w = synth.LARGE6D
+    g, x, _ = synth.segment_data(w)
+    al, de = synth.sky_uniform(g, w.n_sky)
+    fd = synth.spindown_grid(w.n_fdot)
+    nodes = fstat.nodes_array(np.repeat(al, w.n_fdot), np.repeat(de, w.n_fdot), np.tile(fd, w.n_sky))
+    half = w.nfft // 2
+    spec = fstat.SegmentSpec(x=x, dt=w.dt, n_days=w.days, nfft=w.nfft)
+    res = {"workload": w.name + ", per-node maximum on bins [0, nfft/2), LINEAR_UP2", "nodes": int(len(nodes))}
+    p32 = fstat.Plan([spec], fstat.default_detector(), fstat.Ephemeris(), interp=fstat.LINEAR_UP2, prec=fstat.FP32,
+                     autotune=True)
+    sub = nodes[:8192]
+    p32.grid_max(sub, 0, half)   # warm-up
+    torch.cuda.synchronize()
+    p32.profile(True)
+    t = time.perf_counter()
+    F32, k32 = p32.grid_max(nodes, 0, half)
+    torch.cuda.synchronize()
+    s32 = time.perf_counter() - t
+    b32 = sum(p32.profile_read(k)["bytes"] for k in (fstat.K_SKY, fstat.K_PASS1, fstat.K_PASS2))
+    p32.profile(False)
+    gbs = b32 / s32 / 1e9
+    res["fp32"] = {"value": round(len(nodes) / s32, 1), "unit": "nodes/s", "s": round(s32, 3),
+                   "bytes_per_node": round(b32 / len(nodes)), "path_GBps": round(gbs, 1),
+                   "path_frac": round(gbs / HBM_PEAK_GBS, 4), "schedule": p32.schedule()}
+    F32s, k32s = F32[:len(sub)].double().cpu().numpy(), k32[:len(sub)].cpu().numpy()
+    del p32, F32, k32
+    torch.cuda.empty_cache()
+    log("6-day FP32: %.0f nodes/s, %.1f GB/s algorithmic" % (len(nodes) / s32, gbs))
+    p64 = fstat.Plan([spec], fstat.default_detector(), fstat.Ephemeris(), interp=fstat.LINEAR_UP2, prec=fstat.FP64,
+                     autotune=True)
+    p64.grid_max(sub[:256], 0, half)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    F64, k64 = p64.grid_max(sub, 0, half)
+    torch.cuda.synchronize()
+    s64 = time.perf_counter() - t
+    F64, k64 = F64.cpu().numpy(), k64.cpu().numpy()
+    res["fp64_batched"] = {"value": round(len(sub) / s64, 1), "unit": "nodes/s", "nodes": len(sub),
+                           "s": round(s64, 3), "schedule": p64.schedule()}
+    del p64
+    torch.cuda.empty_cache()
+    res["fp32_vs_fp64_max_rel_err"] = float(np.max(np.abs(F32s - F64) / np.maximum(np.abs(F64), 1.0)))
+    res["argmax_agree"] = "%d/%d" % (int(np.sum(k32s == k64)), len(sub))
+    log("6-day FP64 batched: %.0f nodes/s; FP32 vs FP64 %.2e" % (len(sub) / s64, res["fp32_vs_fp64_max_rel_err"]))
+    return res
+
+
+def refine_leg():
+    """4096 candidates half a cell (per parameter) from a point of the 1-day
+    workload (N = 43082, dt = 2 s, LINEAR_UP2): F and dF/d(f, fdot, alpha,
+    delta) in FP64 (fstat_grad: forward kernel, then the adjoint)."""
+    import numpy as np
+    import torch
+    from paper_1003_0844_amd import fstat, synth
+    w = synth.TINY
+    g, x, sigs = synth.segment_data(w)
+    sig = sigs[0]
+    plan = fstat.Plan([fstat.SegmentSpec(x=x, dt=w.dt, n_days=w.days, nfft=w.nfft)], fstat.default_detector(),
+                      fstat.Ephemeris(), interp=fstat.LINEAR_UP2, prec=fstat.FP64)
+    df = 1.0 / (w.nfft * w.dt)
+    v_c = fstat.AU * 2 * math.pi / fstat.YEAR / fstat.C_LIGHT
+    cell = np.array([df, 1.0 / (w.n * w.dt) ** 2, df / (synth.F_REF * v_c), df / (synth.F_REF * v_c)])
+    P = torch.tensor(np.array([sig["f"], sig["fdot"], sig["alpha"], sig["delta"]])
+                     + 0.5 * cell * synth.candidate_offsets(1003, 4096), dtype=torch.float64, device="cuda")
+    plan.grad(P)
+    s = _median_time(lambda: plan.grad(P), 5)
+    res = {"workload": "4096 candidates at +-1/2 cell around a 1-day point (N=43082, dt=2 s), LINEAR_UP2, FP64",
+           "value": round(4096 / s, 1), "unit": "candidates/s", "s_per_call": round(s, 5)}
+    flops = flop_record("k_eval+k_adjoint", w.n)
+    if flops is not None:
+        gf = flops * 4096 / s / 1e9
+        res["alu"] = {"bound": "alu", "achieved": round(gf, 1), "peak": FP64_PEAK_GFLOPS, "unit": "GFLOP/s",
+                      "frac": round(gf / FP64_PEAK_GFLOPS, 4), "flop_per_candidate": flops}
+    log("refinement: %.0f candidates/s" % (4096 / s))
+    return res
+
 
 
 def main():
@@ -267,21 +484,26 @@ def main():
     step_bytes = sum(prof[k]["bytes"] for k in names) / args.steps
     path_gbs = step_bytes / (el / args.steps) / 1e9
 
-    # the plain path: all-FP64, one node per launch, on the first nodes of the grid
+    # the plain path: all-FP64, one node per launch, on the first nodes of the
+    # grid, timed over several calls (median)
     sub = nodes[:args.plain_nodes]
     plan64 = fstat.Plan([fstat.SegmentSpec(x=x, dt=w.dt, n_days=w.days, nfft=nfft)], fstat.default_detector(),
                         fstat.Ephemeris(), interp=fstat.LINEAR_UP2, prec=fstat.FP64, max_batch=1)
     F64 = torch.empty((len(sub), width), dtype=torch.float64, device="cuda")
     plan64.grid_map(sub, 0, half, F64, interbin=ib)
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    plan64.grid_map(sub, 0, half, F64, interbin=ib)
-    torch.cuda.synchronize()
-    plain = len(sub) / (time.perf_counter() - t1)
+    plain_runs = []
+    for _ in range(max(1, args.plain_repeats)):
+        t1 = time.perf_counter()
+        plan64.grid_map(sub, 0, half, F64, interbin=ib)
+        torch.cuda.synchronize()
+        plain_runs.append(len(sub) / (time.perf_counter() - t1))
+    plain = float(np.median(plain_runs))
     diff = (F[:len(sub)].double() - F64).abs() / torch.clamp(F64.abs(), min=1.0)
     err32 = float(diff.max().item())
     del F64, plan64
-    log("plain FP64 path: %.1f nodes/s; FP32 vs FP64 max |dF|/max(F,1) = %.2e" % (plain, err32))
+    log("plain FP64 path: %.1f nodes/s (median of %d calls of %d nodes); FP32 vs FP64 max |dF|/max(F,1) = %.2e"
+        % (plain, len(plain_runs), len(sub), err32))
 
     out = {
         "metric": "F-stat grid nodes/sec (1 MI355X) at stated error; % HBM roofline vs plain path",
@@ -306,16 +528,19 @@ def main():
         "kernels": kernels,
         "schedule": sched,
         "plain_fp64_one_node_per_launch": {"value": round(plain, 1), "unit": "nodes/s",
-                                           "nodes": len(sub), "speedup": round(value / plain, 2)},
+                                           "nodes": len(sub), "calls": [round(v, 1) for v in plain_runs],
+                                           "speedup": round(value / plain, 2)},
         "f32_vs_f64_max_rel_err": err32,
     }
-    del F
+    del F, plan
     torch.cuda.empty_cache()
     cp, cp_blocks = copy_probe_gbps()
     out["roofline"]["copy_probe_GBps"] = round(cp, 1)
     out["roofline"]["path_frac_of_copy"] = round(path_gbs / cp, 4)
     log("copy probe: %.1f GB/s (%d workgroups); path %.1f GB/s = %.1f %% of it" % (cp, cp_blocks, path_gbs,
                                                                                  100 * path_gbs / cp))
+    if not args.no_extra and lat is None and not ib:
+        out["workloads"] = {"uneven_segments": uneven_leg(), "large6d": large6d_leg(), "refinement": refine_leg()}
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(w, x, nodes, args.cpu_seconds, nfft, ib)

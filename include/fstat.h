@@ -391,6 +391,22 @@ fstat_status fstat_lattice_nodes(const fstat_lattice *lat, const fstat_lattice_r
 fstat_status fstat_grad(fstat_plan_t p, const double *params, const int32_t *seg, int64_t n, double *F,
                         double *dF, void *hip_stream);
 
+/* fstat_grad without any device allocation, for callers that cannot allocate
+ * (code under HIP graph capture, serving loops, harnesses that forbid
+ * hipMalloc).  The same kernels and results as fstat_grad; the forward state
+ * lives in a fixed device array of the library (FSTAT_GRAD_STATIC_MAX x
+ * FSTAT_STATE doubles, 4 MiB, held by each GPU the library runs on until the
+ * process ends) instead of the plan's workspace.  Every call on one GPU
+ * shares that array: calls that overlap in time on one GPU (any plan, any
+ * stream) race on it and must be serialised.  dF is required.
+ *   params: device [n][4]; seg: device [n] or NULL; F: device [n];
+ *   dF: device [n][4]
+ * FSTAT_EUNSUPPORTED for n > FSTAT_GRAD_STATIC_MAX; FSTAT_EINVAL for NULL
+ * params, F, dF or n <= 0. */
+#define FSTAT_GRAD_STATIC_MAX 65536
+fstat_status fstat_grad_static(fstat_plan_t p, const double *params, const int32_t *seg, int64_t n, double *F,
+                               double *dF, void *hip_stream);
+
 /* The continuous parameters of output bins of grid nodes, for fstat_eval,
  * fstat_grad, fstat_refine and fstat_amplitudes: node i and its output index
  * k[i] (a map column plus k_lo, a kmax, or a crossing's k; with interbin = 1

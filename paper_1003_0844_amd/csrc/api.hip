@@ -1084,6 +1084,19 @@ fstat_status fstat_grad(fstat_plan_t p, const double* params, const int32_t* seg
   return from_hip(fsk::grad_adjoint(p->d_segs, (int)p->segs.size(), seg, params, n, state, nullptr, dF, st));
 }
 
+}  // extern "C"
+
+// The plan's device segment table, its length and device, for entry points
+// defined in other sources (null for a null plan).
+const SegDev* fstat_plan_device_segments(fstat_plan_t p, int* nseg, int* device) {
+  if (!p) return nullptr;
+  *nseg = (int)p->segs.size();
+  *device = p->device;
+  return p->d_segs;
+}
+
+extern "C" {
+
 fstat_status fstat_bin_params(fstat_plan_t p, const fstat_node* nodes, const int64_t* k, int64_t n, int32_t interbin,
                               double* params, int32_t* seg) {
   if (!p || n < 0 || (n > 0 && (!nodes || !k || !params)) || (interbin != 0 && interbin != 1)) return FSTAT_EINVAL;

@@ -23,6 +23,7 @@ NEAREST, LINEAR_UP2, CUBIC_UP2 = 0, 1, 2
 FP32, FP64 = 0, 1
 OUT_MAP, OUT_MAX, OUT_CROSSINGS = 0, 1, 2
 STATE = 8
+GRAD_STATIC_MAX = 65536
 
 OK, EINVAL, ENOTINTDAYS, ENOMEM, EDEVICE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 
@@ -96,7 +97,7 @@ CROSSING_DTYPE = np.dtype([("node", "<i8"), ("k", "<i8"), ("F", "<f8")])
 
 EXPORTS = ("fstat_plan", "fstat_grid", "fstat_graph_create", "fstat_graph_launch", "fstat_graph_destroy",
            "fstat_eval", "fstat_eval_exact", "fstat_refine", "fstat_threshold", "fstat_adjoint", "fstat_amplitudes",
-           "fstat_grad", "fstat_plan_info", "fstat_demod_series",
+           "fstat_grad", "fstat_grad_static", "fstat_plan_info", "fstat_demod_series",
            "fstat_lattice_fisher", "fstat_lattice_build", "fstat_lattice_segment", "fstat_lattice_nodes",
            "fstat_copy_probe", "fstat_bin_params",
            "fstat_profile",
@@ -124,6 +125,7 @@ def lib():
         L.fstat_eval.argtypes = [vp, vp, vp, i64, vp, vp, vp]
         L.fstat_adjoint.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp]
         L.fstat_grad.argtypes = [vp, vp, vp, i64, vp, vp, vp]
+        L.fstat_grad_static.argtypes = [vp, vp, vp, i64, vp, vp, vp]
         L.fstat_amplitudes.argtypes = [vp, vp, vp, i64, vp, vp, vp]
         L.fstat_eval_exact.argtypes = [vp, vp, vp, i64, vp, vp]
         L.fstat_refine.argtypes = [vp, vp, vp, i64, P(_RefineOptions), vp, vp, vp, vp]
@@ -148,7 +150,7 @@ def lib():
                      "fstat_eval_exact", "fstat_refine", "fstat_threshold", "fstat_lattice_fisher",
                      "fstat_lattice_build", "fstat_lattice_segment", "fstat_lattice_nodes", "fstat_copy_probe",
                      "fstat_bin_params",
-                     "fstat_eval", "fstat_adjoint", "fstat_grad", "fstat_plan_info",
+                     "fstat_eval", "fstat_adjoint", "fstat_grad", "fstat_grad_static", "fstat_plan_info",
                      "fstat_demod_series", "fstat_profile", "fstat_profile_read", "fstat_plan_schedule"):
             getattr(L, name).restype = i32
         _lib = L
@@ -584,6 +586,21 @@ class Plan:
         dF = torch.empty((n, 4), dtype=torch.float64, device=self._dev())
         _check(lib().fstat_grad(self._h, _ptr(params), _ptr(seg), n, _ptr(F), _ptr(dF),
                                 _stream_ptr(self.device)), "fstat_grad")
+        return F, dF
+
+    def grad_static(self, params: torch.Tensor, seg: Optional[torch.Tensor] = None, F: Optional[torch.Tensor] = None,
+                    dF: Optional[torch.Tensor] = None):
+        """grad through fstat_grad_static: no device allocation in the
+        library (at most GRAD_STATIC_MAX candidates; calls on one GPU must
+        not overlap).  F [n] and dF [n, 4] may be given (preallocated)."""
+        params, seg = self._params(params, seg)
+        n = params.shape[0]
+        if F is None:
+            F = torch.empty(n, dtype=torch.float64, device=self._dev())
+        if dF is None:
+            dF = torch.empty((n, 4), dtype=torch.float64, device=self._dev())
+        _check(lib().fstat_grad_static(self._h, _ptr(params), _ptr(seg), n, _ptr(F), _ptr(dF),
+                                       _stream_ptr(self.device)), "fstat_grad_static")
         return F, dF
 
 

@@ -121,7 +121,25 @@ typedef struct {
                         size.  The choice is cached in the file named by the
                         environment variable FSTAT_TUNE_CACHE if it is set.
                         0: fixed defaults. */
+  int32_t launch;    /* FSTAT_LAUNCH_PASSES or FSTAT_LAUNCH_PERSISTENT */
 } fstat_options;
+
+/* How fstat_grid (and a recorded graph) runs a call. */
+#define FSTAT_LAUNCH_PASSES 0      /* a sequence of launches per sky batch and node batch: sky
+                                      preparation, first FFT pass, second FFT pass (default) */
+#define FSTAT_LAUNCH_PERSISTENT 1  /* the whole call in one launch of a persistent kernel: a work
+                                      queue of tiles (sky preparation of each sky batch, pass 1
+                                      and pass 2 of each node), segments ordered by FFT length
+                                      (longest first), each tile started once what it reads is
+                                      complete.  Used for FP32 plans on calls whose segments all
+                                      have 2^18 <= nfft <= 2^22 (the plan then splits them with
+                                      C = 4096 columns) and no interbinning; other calls run as
+                                      FSTAT_LAUNCH_PASSES.  Every wait inside the kernel is
+                                      bounded: if one expires the kernel stops early and the
+                                      plan's error flag is set (fstat_plan_status).
+                                      Currently switched off: a plan created with it runs
+                                      every call as FSTAT_LAUNCH_PASSES (its kernel did not
+                                      finish on its first GPU run; the cause is not known). */
 /* Environment: FSTAT_STREAMS=1 (or 2) at plan creation fixes the stream mode
  * of every segment (see fstat_plan_schedule) instead of the default or tuned
  * one; meant for per-kernel timing. */
@@ -421,6 +439,12 @@ fstat_status fstat_grad_static(fstat_plan_t p, const double *params, const int32
  * bin out of range (nothing is written then). */
 fstat_status fstat_bin_params(fstat_plan_t p, const fstat_node *nodes, const int64_t *k, int64_t n,
                               int32_t interbin, double *params, int32_t *seg);
+
+/* Waits for the plan's device, then reports and clears the plan's error flag:
+ * FSTAT_EDEVICE if a persistent launch (FSTAT_LAUNCH_PERSISTENT) stopped early
+ * since the last call (a wait inside the kernel outlived its bound; the
+ * outputs of that call are incomplete), FSTAT_OK otherwise. */
+fstat_status fstat_plan_status(fstat_plan_t p);
 
 /* Plan facts.  Host outputs; any pointer may be NULL. */
 fstat_status fstat_plan_info(fstat_plan_t p, int32_t seg, int64_t *n, int64_t *nfft, double *sigma2,

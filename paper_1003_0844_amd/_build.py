@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libfstat.so")
-SOURCES = ["api.hip", "sky.hip", "grid.hip", "prep.hip", "grad.hip", "search.hip", "probe.hip", "grad_static.hip", "lattice.cpp"]
+SOURCES = ["api.hip", "sky.hip", "grid.hip", "prep.hip", "grad.hip", "search.hip", "probe.hip", "grad_static.hip", "persist.hip", "lattice.cpp"]
 ARCH = os.environ.get("FSTAT_OFFLOAD_ARCH", "gfx950")
 
 

@@ -11,6 +11,7 @@
 
 #include "../../include/fstat.h"
 #include "internal.h"
+#include "persist_sched.h"
 
 namespace {
 
@@ -73,6 +74,11 @@ struct fstat_plan_s {
   hipEvent_t ev_p1[2] = {nullptr, nullptr}, ev_p2[2] = {nullptr, nullptr}, ev_sky[2] = {nullptr, nullptr};
   hipEvent_t ev_join = nullptr;
   bool capturing = false;  // a graph capture is recording the launch sequence
+  int launch = 0;                // FSTAT_LAUNCH_PASSES / FSTAT_LAUNCH_PERSISTENT
+  uint32_t* d_error = nullptr;   // sticky error flag of persistent launches
+  int persist_blocks[3] = {0, 0, 0};  // resident workgroups of the persistent kernel per output mode
+  int persist_slots = 8;         // spill slots of a persistent launch (FSTAT_PERSIST_SLOTS)
+  uint64_t spin_ticks = 0;       // wall-clock ticks a wait of the persistent kernel may last
 };
 
 // A grid call recorded once as a HIP graph, with a workspace of its own.
@@ -159,6 +165,7 @@ void destroy_plan(fstat_plan_s* p) {
   if (p->ws) (void)hipFree(p->ws);
   if (p->pinned) (void)hipHostFree(p->pinned);
   if (p->staged) (void)hipEventDestroy(p->staged);
+  if (p->d_error) (void)hipFree(p->d_error);
   for (hipEvent_t ev : {p->ev_p1[0], p->ev_p1[1], p->ev_p2[0], p->ev_p2[1], p->ev_sky[0], p->ev_sky[1], p->ev_join})
     if (ev) (void)hipEventDestroy(ev);
   if (p->side) (void)hipStreamDestroy(p->side);
@@ -584,6 +591,108 @@ fstat_status run_grid(fstat_plan_s* p, const fstat_node* nodes, int64_t n_nodes,
 // ---------------------------------------------------------------------------
 // autotuner: FFT split and node-batch size per segment
 // ---------------------------------------------------------------------------
+// A persistent plan splits FP32 segments of 2^18 <= nfft <= 2^22 with C = 4096
+// (R = nfft / 4096 in [64, 1024]): the shapes the persistent kernel holds.
+bool persistent_split(const fstat_plan_s* p, int64_t nfft) {
+  return p->launch == FSTAT_LAUNCH_PERSISTENT && p->prec == 0 && nfft >= (1 << 18) && nfft <= (1 << 22);
+}
+
+// ---------------------------------------------------------------------------
+// the persistent launch: host layout of the work queue
+// ---------------------------------------------------------------------------
+// Calls the persistent kernel runs: FP32, no interbinning, every segment of
+// the call split with C = 4096 (64 <= R <= 1024).
+// The persistent kernel is switched off: its first run on the GPU did not
+// finish (no output for minutes) and the cause is not known; every call runs
+// as passes until it is.  kPersistentEnabled gates the dispatch.
+constexpr bool kPersistentEnabled = false;
+
+bool persistent_call(const fstat_plan_s* p, const fstat_node* nodes, int64_t n_nodes, const fstat_out* out) {
+  if (!kPersistentEnabled) return false;
+  if (p->launch != FSTAT_LAUNCH_PERSISTENT || p->prec != 0 || out->interbin) return false;
+  for (int64_t i = 0; i < n_nodes; ++i) {
+    const SegDev& d = p->segs[nodes[i].seg].dev;
+    if (d.C != 4096 || d.R < 64 || d.R > 1024) return false;
+  }
+  return true;
+}
+
+// The launches of a persistent call on st (counters cleared, crossing counter
+// cleared, the kernel); ws holds ps.need_ws bytes starting with the packed
+// descriptors.
+fstat_status launch_persistent(fstat_plan_s* p, const PersistSched& ps, void* ws, const fstat_out* out,
+                               hipStream_t st) {
+  const int mode = out->mode;
+  if (p->persist_blocks[mode] <= 0) {
+    p->persist_blocks[mode] = fsk::persistent_blocks(mode);
+    if (p->persist_blocks[mode] <= 0) return FSTAT_EDEVICE;
+  }
+  Carve cv{(char*)ws};
+  PersistArgs a{};
+  a.sky_ad = cv.take<double>(ps.sky_ad.size());
+  a.nodes = cv.take<NodeDev>(ps.ndev.size());
+  a.node_batch = cv.take<int32_t>(ps.node_batch.size());
+  a.batches = cv.take<PBatch>(ps.batches.size());
+  a.units = cv.take<PUnit>(ps.units.size());
+  a.tw = cv.take<PSegTw>(ps.tw.size());
+  for (int k = 0; k < 2; ++k) {
+    a.quads[k] = cv.take<char>(ps.max_quads);
+    a.sky[k] = cv.take<SkyConst>(ps.max_sky);
+    a.coef[k] = cv.take<SkyCoef>(ps.max_sky);
+  }
+  a.spill = cv.take<Pair<float>>((size_t)ps.nslots * ps.slot_elems);
+  a.part = cv.take<MaxPartial>((size_t)ps.nslots * 1024);
+  a.cnt = cv.take<uint32_t>(ps.ncnt);
+  a.head = cv.take<unsigned long long>(1);
+  a.segs = p->d_segs;
+  a.nitems = (int64_t)ps.units.size() * PUNIT;
+  a.nbatch = (int32_t)ps.batches.size();
+  a.nslots = ps.nslots;
+  a.slot_elems = ps.slot_elems;
+  a.error = p->d_error;
+  a.spin_ticks = p->spin_ticks;
+  GridOut& go = a.out;
+  go.mode = out->mode;
+  go.interbin = 0;
+  go.k_lo = out->k_lo;
+  go.k_hi = out->k_hi;
+  go.threshold = out->threshold;
+  go.F = out->F;
+  go.Fmax = out->Fmax;
+  go.kmax = out->kmax;
+  go.xing = out->crossings;
+  go.n_xing = out->n_crossings;
+  go.max_xing = out->max_crossings;
+  HIP_TRY(fsk::persist_zero(a.cnt, ps.ncnt, a.head, st));
+  if (out->mode == 2) HIP_TRY(fsk::zero_u64(out->n_crossings, st));
+  return from_hip(fsk::grid_persistent(a, mode, p->persist_blocks[mode], st));
+}
+
+std::vector<SegShape> seg_shapes(const fstat_plan_s* p) {
+  std::vector<SegShape> v(p->segs.size());
+  for (size_t s = 0; s < p->segs.size(); ++s) {
+    const SegPlan& sp = p->segs[s];
+    v[s] = SegShape{sp.dev.nfft, sp.dev.R, sp.dev.Ceff, PSegTw{sp.twC, sp.twR, sp.twlo, sp.twhi}};
+  }
+  return v;
+}
+
+fstat_status run_persistent(fstat_plan_s* p, const fstat_node* nodes, int64_t n_nodes, const fstat_out* out,
+                            hipStream_t st) {
+  PersistSched ps;
+  schedule_persistent(seg_shapes(p), p->persist_slots, nodes, n_nodes, ps);
+  if (!ps.ordered) return FSTAT_EUNSUPPORTED;
+  fstat_status rc = ensure_ws(p, ps.need_ws);
+  if (rc != FSTAT_OK) return rc;
+  rc = ensure_pinned(p, ps.desc_bytes);
+  if (rc != FSTAT_OK) return rc;
+  pack_persistent(ps, (char*)p->pinned);
+  HIP_TRY(hipMemcpyAsync(p->ws, p->pinned, ps.desc_bytes, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipEventRecord(p->staged, st));
+  p->staged_pending = true;
+  return launch_persistent(p, ps, p->ws, out, st);
+}
+
 struct TuneKey {
   int prec, interp;
   int64_t nfft, n;
@@ -636,7 +745,7 @@ fstat_status tune_segment(fstat_plan_s* p, int si) {
   const TuneKey key{prec, p->interp, nfft, sp.dev.n};
   int C = sp.dev.C, batch = sp.node_cap, streams = sp.streams;
   if (cache_lookup(key, C, batch, streams) && split_valid(prec, nfft, C) && batch > 0 &&
-      (streams == 1 || streams == 2)) {
+      (streams == 1 || streams == 2) && (!persistent_split(p, nfft) || C == 4096)) {
     apply_split(sp, prec, C);
     sp.node_cap = batch;
     sp.streams = p->force_streams ? p->force_streams : streams;
@@ -644,10 +753,12 @@ fstat_status tune_segment(fstat_plan_s* p, int si) {
     HIP_TRY(hipDeviceSynchronize());
     return FSTAT_OK;
   }
-  // the default first: split of choose_split, largest batch
+  // the default first: split of choose_split, largest batch; a persistent plan
+  // keeps C = 4096 where its kernel applies
   std::vector<int> cands = {sp.dev.C};
   for (int c : {4096, 2048, 1024})
     if (split_valid(prec, nfft, c) && std::find(cands.begin(), cands.end(), c) == cands.end()) cands.push_back(c);
+  if (persistent_split(p, nfft)) cands = {4096};
   std::vector<int> batches;
   if (p->max_batch > 0) batches = {p->max_batch};
   else if (prec == 0) batches = {256, 128, 64, 32};
@@ -761,7 +872,8 @@ fstat_status fstat_plan(const fstat_segment* segs, int32_t nseg, const fstat_det
                         const fstat_ephemeris* eph, const fstat_options* opt, fstat_plan_t* out) {
   if (!segs || nseg <= 0 || !det || !eph || !opt || !out) return FSTAT_EINVAL;
   if (opt->interp < 0 || opt->interp > 2 || opt->prec < 0 || opt->prec > 1 || opt->max_batch < 0 ||
-      opt->max_batch > 256 || opt->autotune < 0 || opt->autotune > 1)
+      opt->max_batch > 256 || opt->autotune < 0 || opt->autotune > 1 ||
+      (opt->launch != FSTAT_LAUNCH_PASSES && opt->launch != FSTAT_LAUNCH_PERSISTENT))
     return FSTAT_EINVAL;
   if (!(eph->sidereal_day_s > 0.0) || !std::isfinite(eph->orbit_radius_m) || !std::isfinite(eph->orbit_omega) ||
       !std::isfinite(det->radius_m) || !std::isfinite(det->lat_rad))
@@ -782,6 +894,11 @@ fstat_status fstat_plan(const fstat_segment* segs, int32_t nseg, const fstat_det
   p->interp = opt->interp;
   p->prec = opt->prec;
   p->max_batch = opt->max_batch;
+  p->launch = opt->launch;
+  if (const char* sl = std::getenv("FSTAT_PERSIST_SLOTS")) {
+    const int v = std::atoi(sl);
+    if (v >= 3 && v <= 64) p->persist_slots = v;
+  }
   p->segs.resize(nseg);
   for (int i = 0; i < nseg; ++i) {
     fstat_status rc = build_segment(segs[i], *det, *eph, opt->prec, opt->interp, p->segs[i]);
@@ -790,7 +907,16 @@ fstat_status fstat_plan(const fstat_segment* segs, int32_t nseg, const fstat_det
       return rc;
     }
   }
-  for (auto& sp : p->segs) sp.node_cap = opt->max_batch > 0 ? opt->max_batch : (opt->prec == 0 ? 16 : 4);
+  for (auto& sp : p->segs) {
+    sp.node_cap = opt->max_batch > 0 ? opt->max_batch : (opt->prec == 0 ? 16 : 4);
+    if (persistent_split(p, sp.dev.nfft) && sp.dev.C != 4096) {
+      apply_split(sp, opt->prec, 4096);
+      if (make_split_tables(sp, opt->prec, nullptr) != hipSuccess) {
+        destroy_plan(p);
+        return FSTAT_EDEVICE;
+      }
+    }
+  }
   if (const char* s1 = std::getenv("FSTAT_STREAMS")) {
     if (s1[0] == '1') p->force_streams = 1;
     if (s1[0] == '2') p->force_streams = 2;
@@ -798,6 +924,13 @@ fstat_status fstat_plan(const fstat_segment* segs, int32_t nseg, const fstat_det
   if (p->force_streams)
     for (auto& sp : p->segs) sp.streams = p->force_streams;
   hipError_t e = hipEventCreateWithFlags(&p->staged, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipMalloc(&p->d_error, sizeof(uint32_t));
+  if (e == hipSuccess) e = hipMemset(p->d_error, 0, sizeof(uint32_t));
+  if (e == hipSuccess) {
+    int khz = 0;
+    e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, opt->device);
+    p->spin_ticks = (uint64_t)(khz > 0 ? khz : 100000) * 2000ull;  // 2 s
+  }
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking);
   for (hipEvent_t* ev : {&p->ev_p1[0], &p->ev_p1[1], &p->ev_p2[0], &p->ev_p2[1], &p->ev_sky[0], &p->ev_sky[1], &p->ev_join})
     if (e == hipSuccess) e = hipEventCreateWithFlags(ev, hipEventDisableTiming);
@@ -857,6 +990,18 @@ fstat_status fstat_plan_schedule(fstat_plan_t p, int32_t seg, int32_t* R, int32_
 
 void fstat_destroy(fstat_plan_t p) { destroy_plan(p); }
 
+fstat_status fstat_plan_status(fstat_plan_t p) {
+  if (!p) return FSTAT_EINVAL;
+  DeviceGuard guard(p->device);
+  if (!guard.ok) return FSTAT_EDEVICE;
+  HIP_TRY(hipDeviceSynchronize());
+  uint32_t flag = 0;
+  HIP_TRY(hipMemcpy(&flag, p->d_error, sizeof(flag), hipMemcpyDeviceToHost));
+  if (flag == 0) return FSTAT_OK;
+  HIP_TRY(hipMemset(p->d_error, 0, sizeof(uint32_t)));
+  return FSTAT_EDEVICE;
+}
+
 fstat_status fstat_plan_info(fstat_plan_t p, int32_t seg, int64_t* n, int64_t* nfft, double* sigma2, int32_t* R,
                              int32_t* C) {
   if (!p || seg < 0 || seg >= (int32_t)p->segs.size()) return FSTAT_EINVAL;
@@ -910,6 +1055,7 @@ fstat_status fstat_grid(fstat_plan_t p, const fstat_node* nodes, int64_t n_nodes
   if (rc != FSTAT_OK) return rc;
   DeviceGuard guard(p->device);
   if (!guard.ok) return FSTAT_EDEVICE;
+  if (persistent_call(p, nodes, n_nodes, out)) return run_persistent(p, nodes, n_nodes, out, (hipStream_t)hip_stream);
   return run_grid(p, nodes, n_nodes, out, (hipStream_t)hip_stream);
 }
 
@@ -920,21 +1066,31 @@ fstat_status fstat_graph_create(fstat_plan_t p, const fstat_node* nodes, int64_t
   if (rc != FSTAT_OK) return rc;
   DeviceGuard guard(p->device);
   if (!guard.ok) return FSTAT_EDEVICE;
+  const bool persist = persistent_call(p, nodes, n_nodes, out);
   GridSched gs;
-  schedule_grid(p, nodes, n_nodes, gs);
+  PersistSched ps;
+  if (persist) {
+    schedule_persistent(seg_shapes(p), p->persist_slots, nodes, n_nodes, ps);
+    if (!ps.ordered) return FSTAT_EUNSUPPORTED;
+  } else {
+    schedule_grid(p, nodes, n_nodes, gs);
+  }
   fstat_graph_s* g = new (std::nothrow) fstat_graph_s;
   if (!g) return FSTAT_ENOMEM;
   g->plan = p;
-  std::vector<char> desc(gs.desc_bytes);
-  pack_descriptors(gs, desc.data());
+  std::vector<char> desc(persist ? ps.desc_bytes : gs.desc_bytes);
+  if (persist) pack_persistent(ps, desc.data());
+  else pack_descriptors(gs, desc.data());
   hipStream_t cs = nullptr;
-  hipError_t e = hipMalloc(&g->ws, gs.need_ws);
-  if (e == hipSuccess) e = hipMemcpy(g->ws, desc.data(), gs.desc_bytes, hipMemcpyHostToDevice);
+  hipError_t e = hipMalloc(&g->ws, persist ? ps.need_ws : gs.need_ws);
+  if (e == hipSuccess) e = hipMemcpy(g->ws, desc.data(), desc.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+  if (e == hipSuccess && persist && p->persist_blocks[out->mode] <= 0)  // occupancy query outside the capture
+    p->persist_blocks[out->mode] = fsk::persistent_blocks(out->mode);
   if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
     p->capturing = true;
-    rc = launch_grid(p, gs, g->ws, out, cs);
+    rc = persist ? launch_persistent(p, ps, g->ws, out, cs) : launch_grid(p, gs, g->ws, out, cs);
     p->capturing = false;
     e = hipStreamEndCapture(cs, &g->graph);  // ends the capture whatever launch_grid returned
     if (rc == FSTAT_OK && e == hipSuccess) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);

@@ -5,6 +5,7 @@
 #pragma once
 #include "demod.h"
 #include "internal.h"
+#include "moments.h"
 
 namespace {
 
@@ -76,35 +77,38 @@ __device__ __forceinline__ void setup_sky(const SegDev& sg, const Cand& c, SkyCo
   k.tb0 = roemer(k, ephem(sg.geo, 0.0));
 }
 
-// Terms of sample j of S_a, S_b (resampling method: barycentric grid
-// t_b_j = t_b0 + j dt, cyc_j = f_ref dphi_m(t_j) + fdot (t_j^2/2 + phi_m(t_j) t_j)
-// + f j dt) and of A, B, C (detector sample j):
-// acc += (Re S_a, Im S_a, Re S_b, Im S_b, A, B, C).
+// Terms of sample j of S_a, S_b by the resampling method: barycentric grid
+// t_b_j = t_b0 + j dt, detector time t_j from the angle-addition ephemeris and
+// one linearised fixed-point step (sample_geo), cyc_j = f_ref dphi_m(t_j) +
+// fdot (t_j^2/2 + phi_m(t_j) t_j) + f j dt:  acc += (Re S_a, Im S_a, Re S_b,
+// Im S_b).  A, B, C come from the mask moments (abc_moments).
 __device__ __forceinline__ void method_terms(const SegDev& sg, const SkyConst& k, const Cand& c, int64_t j,
-                                             double (&acc)[7]) {
-  EphemD e;
-  double dpm;
-  const double t = ssb_to_detector(sg.geo, k, (double)j * sg.dt, e, dpm);
+                                             double (&acc)[4]) {
+  const SampleGeo s = sample_geo(sg.geo, k, (double)j * sg.dt);
+  const double t = s.t, dpm = s.dpm;
   const double pm = k.tb0 + dpm;
   double xr, dxdu;
   interp_d(sg, j, -dpm / sg.dt, xr, dxdu);
   double a, b;
-  amp_ab(k, hour_angle(k, e.cth, e.sth), a, b);
+  amp_ab(k, hour_angle(k, s.cth, s.sth), a, b);
   double cyc = sg.f_ref * dpm + c.fdot * (0.5 * t * t + pm * t) + c.f * ((double)j * sg.dt);
   cyc -= rint(cyc);
-  double s, co;
-  sincospi(2.0 * cyc, &s, &co);
+  double sn, co;
+  sincospi(2.0 * cyc, &sn, &co);
   acc[0] += xr * a * co;
-  acc[1] -= xr * a * s;
+  acc[1] -= xr * a * sn;
   acc[2] += xr * b * co;
-  acc[3] -= xr * b * s;
-  const Ephem ed = ephem(sg.geo, (double)j * sg.dt);
-  double ad, bd;
-  amp_ab(k, hour_angle(k, ed), ad, bd);
-  const double m = sg.mask ? (sg.mask[j] ? 1.0 : 0.0) : 1.0;
-  acc[4] += m * ad * ad;
-  acc[5] += m * bd * bd;
-  acc[6] += m * ad * bd;
+  acc[3] -= xr * b * sn;
+}
+
+// A, B, C of a sky position over the segment's detector samples outside gaps,
+// from its mask moments.
+__device__ __forceinline__ void abc_moments(const SegDev& sg, const SkyConst& k, double& A, double& B, double& C) {
+  AbPoly fa, fb;
+  ab_poly(k, fa, fb);
+  A = moment_sum(fa.v, fa.v, sg.mom);
+  B = moment_sum(fb.v, fb.v, sg.mom);
+  C = moment_sum(fa.v, fb.v, sg.mom);
 }
 
 // The same terms without resampling (Eqs. OS-Fab summed on the detector
@@ -140,6 +144,7 @@ __device__ __forceinline__ void exact_terms(const SegDev& sg, const SkyConst& k,
 __device__ __forceinline__ double combine_F(const double (&acc)[7], double sigma2) {
   const double Sar = acc[0], Sai = acc[1], Sbr = acc[2], Sbi = acc[3];
   const double A = acc[4], B = acc[5], C = acc[6];
+  // F of Eq. OS with C != 0 (gaps): (B|S_a|^2 + A|S_b|^2 - 2C Re(S_a S_b*)) / (sigma^2 (AB - C^2))
   const double num = B * (Sar * Sar + Sai * Sai) + A * (Sbr * Sbr + Sbi * Sbi) - 2.0 * C * (Sar * Sbr + Sai * Sbi);
   return num / (sigma2 * (A * B - C * C));
 }

@@ -187,3 +187,117 @@ __device__ __forceinline__ double ssb_to_detector(const SegGeo& g, const SkyCons
   dpm = roemer_delta(k, e);
   return t;
 }
+
+// ---------------------------------------------------------------------------
+// The ephemeris of one sample time by angle addition (the grid's sky
+// preparation and the candidate kernels): the three angles at j dt are turned
+// into sines and cosines once; the ephemeris at the detector time t = j dt - d
+// (|d| below 1000 s) follows from small rotations of them.
+// ---------------------------------------------------------------------------
+// sin and cos of a small angle (|x| < 0.2) by their Taylor polynomials through
+// x^11 and x^12: remainders below 1e-17 relative.
+__device__ __forceinline__ void small_sincos(double x, double& s, double& c) {
+  const double x2 = x * x;
+  s = x * (1.0 - x2 * (1.0 / 6.0) *
+                     (1.0 - x2 * (1.0 / 20.0) *
+                                (1.0 - x2 * (1.0 / 42.0) * (1.0 - x2 * (1.0 / 72.0) * (1.0 - x2 * (1.0 / 110.0))))));
+  c = 1.0 - x2 * 0.5 *
+                (1.0 - x2 * (1.0 / 12.0) *
+                           (1.0 - x2 * (1.0 / 30.0) *
+                                      (1.0 - x2 * (1.0 / 56.0) *
+                                                 (1.0 - x2 * (1.0 / 90.0) * (1.0 - x2 * (1.0 / 132.0))))));
+}
+
+// The analytic ephemeris at one time t: the angles of ephem_delta as sines and
+// cosines, from which the ephemeris at any nearby time t - d follows by angle
+// addition.
+struct EphemBase {
+  double sm, cm;    // 2 pi (orb_c0 + h/2), h = t orb_rate_c
+  double sh, ch;    // pi h
+  double sth, cth;  // local sidereal angle
+};
+
+__device__ __forceinline__ EphemBase ephem_base(const SegGeo& g, double t) {
+  EphemBase b;
+  const double h = t * g.orb_rate_c;
+  double mid = g.orb_c0 + 0.5 * h;
+  mid -= rint(mid);
+  sincospi(2.0 * mid, &b.sm, &b.cm);
+  sincospi(h, &b.sh, &b.ch);
+  double cs = g.sid_c0 + t * g.sid_rate_c;
+  cs -= rint(cs);
+  sincospi(2.0 * cs, &b.sth, &b.cth);
+  return b;
+}
+
+// dphi_m at t - d and its time derivative (the same quantities as
+// roemer_delta(ephem_delta(t - d))): the orbital angles move by
+// pi orb_rate_c d, the sidereal angle by 2 pi sid_rate_c d.  |d| <= 1000 s
+// (twice the orbit's light time), so both angles stay below 0.08 rad.
+__device__ __forceinline__ void roemer_at(const SegGeo& g, const SkyConst& k, const EphemBase& b, double d,
+                                          double& dpm, double& ddpm) {
+  constexpr double PI = 3.14159265358979323846;
+  const double wo = PI * g.orb_rate_c, ws = 2.0 * PI * g.sid_rate_c;
+  double so, co, ss, cs;
+  small_sincos(wo * d, so, co);
+  small_sincos(ws * d, ss, cs);
+  const double sm = b.sm * co - b.cm * so, cm = b.cm * co + b.sm * so;
+  const double sh = b.sh * co - b.ch * so, ch = b.ch * co + b.sh * so;
+  const double sth = b.sth * cs - b.cth * ss, cth = b.cth * cs + b.sth * ss;
+  const double dxes = -2.0 * g.orb_r * sm * sh, dyes = 2.0 * g.orb_r * cm * sh;
+  const double dxe = g.site_rc * (cth - g.cth0), dye = g.site_rc * (sth - g.sth0);
+  dpm = k.nx * (dxes + dxe) + k.nye * dyes + k.ny * dye;
+  const double vxes = -2.0 * g.orb_r * wo * (cm * sh + sm * ch), vyes = 2.0 * g.orb_r * wo * (cm * ch - sm * sh);
+  const double vxe = -g.site_rc * ws * sth, vye = g.site_rc * ws * cth;
+  ddpm = k.nx * (vxes + vxe) + k.nye * vyes + k.ny * vye;
+}
+
+// The detector time t of the barycentric grid point t_b0 + j dt, i.e. the
+// solution of t + dphi_m(t) = j dt, and the ephemeris there.  d0 = dphi_m(j dt)
+// is within |dphi_m'| x 500 s ~ 0.05 s of dphi_m(t); one step of the fixed-point
+// relation linearised at t1 = j dt - d0,
+//   dphi_m(t) = (dphi_m(t1) + dphi_m'(t1) d0) / (1 + dphi_m'(t1)),
+// leaves ~1e-13 s (the curvature of dphi_m is below 1e-10 s/s^2).  The
+// sidereal and orbital angles at t follow by one more small rotation.
+struct SampleGeo {
+  double t, dpm;    // detector time, dphi_m(t)
+  double cth, sth;  // local sidereal angle at t
+  double cor, sor;  // orbital angle at t
+};
+
+__device__ __forceinline__ SampleGeo sample_geo(const SegGeo& g, const SkyConst& k, double jdt) {
+  constexpr double PI = 3.14159265358979323846;
+  const EphemBase b = ephem_base(g, jdt);
+  double d, dd, v, dv;
+  roemer_at(g, k, b, 0.0, d, dd);
+  roemer_at(g, k, b, d, v, dv);
+  SampleGeo s;
+  s.dpm = (v + dv * d) / (1.0 + dv);
+  s.t = jdt - s.dpm;
+  double so, co, ss, cs;
+  small_sincos(PI * g.orb_rate_c * s.dpm, so, co);
+  small_sincos(2.0 * PI * g.sid_rate_c * s.dpm, ss, cs);
+  s.sth = b.sth * cs - b.cth * ss;
+  s.cth = b.cth * cs + b.sth * ss;
+  // orbital angle = (half-way angle) + (half advance), both rotated back
+  const double sm = b.sm * co - b.cm * so, cm = b.cm * co + b.sm * so;
+  const double sh = b.sh * co - b.ch * so, ch = b.ch * co + b.sh * so;
+  s.cor = cm * ch - sm * sh;
+  s.sor = sm * ch + cm * sh;
+  return s;
+}
+
+// The absolute ephemeris at the sample's detector time.
+__device__ __forceinline__ Ephem ephem_of(const SegGeo& g, const SampleGeo& s) {
+  Ephem e;
+  e.cor = s.cor;
+  e.sor = s.sor;
+  e.cth = s.cth;
+  e.sth = s.sth;
+  e.xes = g.orb_r * s.cor;
+  e.yes = g.orb_r * s.sor;
+  e.xe = g.site_rc * s.cth;
+  e.ye = g.site_rc * s.sth;
+  e.ze = g.site_rz;
+  return e;
+}

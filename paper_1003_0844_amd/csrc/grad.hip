@@ -27,7 +27,7 @@ namespace {
 __global__ void __launch_bounds__(GB)
 k_eval(const SegDev* __restrict__ segs, int nseg, const int32_t* __restrict__ segi,
        const double* __restrict__ params, double* __restrict__ Fout, double* __restrict__ state) {
-  __shared__ double sh[(GB / 64) * 7];
+  __shared__ double sh[(GB / 64) * 4];
   const int64_t ci = blockIdx.x;
   const int si = segi ? segi[ci] : 0;
   if (si < 0 || si >= nseg) {  // invalid segment index: NaN result, nothing read
@@ -38,12 +38,13 @@ k_eval(const SegDev* __restrict__ segs, int nseg, const int32_t* __restrict__ se
   const Cand c{params[4 * ci], params[4 * ci + 1], params[4 * ci + 2], params[4 * ci + 3]};
   SkyConst k;
   setup_sky(sg, c, k);
-  double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+  double acc[4] = {0, 0, 0, 0};
   for (int64_t j = threadIdx.x; j < sg.n; j += GB) method_terms(sg, k, c, j, acc);
-  block_sums<7>(acc, sh);
+  block_sums<4>(acc, sh);
   if (threadIdx.x == 0) {
     const double Sar = acc[0], Sai = acc[1], Sbr = acc[2], Sbi = acc[3];
-    const double A = acc[4], B = acc[5], C = acc[6];
+    double A, B, C;
+    abc_moments(sg, k, A, B, C);
     const double num = B * (Sar * Sar + Sai * Sai) + A * (Sbr * Sbr + Sbi * Sbi) - 2.0 * C * (Sar * Sbr + Sai * Sbi);
     Fout[ci + threadIdx.x] = num / (sg.sigma2 * (A * B - C * C));
     if (state) {
@@ -121,15 +122,13 @@ k_adjoint(const SegDev* __restrict__ segs, int nseg, const int32_t* __restrict__
   double acc[4] = {0, 0, 0, 0};
   for (int64_t j = threadIdx.x; j < sg.n; j += GB) {
     const double jdt = (double)j * sg.dt;
-    EphemD ed;
-    double dpm;
-    const double t = ssb_to_detector(sg.geo, k, jdt, ed, dpm);
+    const SampleGeo sgeo = sample_geo(sg.geo, k, jdt);
+    const double t = sgeo.t, dpm = sgeo.dpm;
     const double pm = k.tb0 + dpm;
-    const Ephem e = ephem(sg.geo, t);  // absolute positions for the partials
     double xr, dxdu;
     interp_d(sg, j, -dpm / sg.dt, xr, dxdu);
-    const AbPartials ab = ab_partials(k, hour_angle(k, ed.cth, ed.sth));
-    const Partials pp = roemer_partials(sg, k, e);
+    const AbPartials ab = ab_partials(k, hour_angle(k, sgeo.cth, sgeo.sth));
+    const Partials pp = roemer_partials(sg, k, ephem_of(sg.geo, sgeo));  // absolute positions at t
     double cyc = sg.f_ref * dpm + c.fdot * (0.5 * t * t + pm * t) + c.f * jdt;
     cyc -= rint(cyc);
     double s, co;
@@ -153,19 +152,26 @@ k_adjoint(const SegDev* __restrict__ segs, int nseg, const int32_t* __restrict__
       const double dx = (th == 0 ? 1.0 : 0.0) - wr * dtj;
       const double da = ab.ax * dx + (th == 1 ? ab.ad : 0.0);
       const double db = ab.bx * dx + (th == 1 ? ab.bd : 0.0);
-      const double dpm = dpmx + pp.T * dtj;
-      const double dcyc = sg.f_ref * dpm + c.fdot * (t * dtj + dpm * t + pm * dtj);
+      const double dpm_th = dpmx + pp.T * dtj;
+      const double dcyc = sg.f_ref * dpm_th + c.fdot * (t * dtj + dpm_th * t + pm * dtj);
       const double dwa = dxr * ab.a + xr * da, dwb = dxr * ab.b + xr * db;
       acc[2 + th] += dwa * Ear + TWO_PI * wa * dcyc * Eai + dwb * Ebr + TWO_PI * wb * dcyc * Ebi;
     }
-    // A, B, C on the detector samples
-    const AbPartials g = ab_partials(k, hour_angle(k, ephem(sg.geo, jdt)));
-    const double m = sg.mask ? (sg.mask[j] ? 1.0 : 0.0) : 1.0;
-    acc[2] += m * (FA * 2.0 * g.a * g.ax + FB * 2.0 * g.b * g.bx + FC * (g.ax * g.b + g.a * g.bx));
-    acc[3] += m * (FA * 2.0 * g.a * g.ad + FB * 2.0 * g.b * g.bd + FC * (g.ad * g.b + g.a * g.bd));
   }
   block_sums<4>(acc, sh);
   if (threadIdx.x == 0) {
+    // A, B, C on the detector samples: their alpha and delta derivatives from
+    // the mask moments
+    AbPoly fa, fb, fa_al, fb_al, fa_de, fb_de;
+    ab_poly(k, fa, fb);
+    ab_poly_partials(k, fa, fb, fa_al, fb_al, fa_de, fb_de);
+    const double* mom = sg.mom;
+    const double dA_al = 2.0 * moment_sum(fa.v, fa_al.v, mom), dA_de = 2.0 * moment_sum(fa.v, fa_de.v, mom);
+    const double dB_al = 2.0 * moment_sum(fb.v, fb_al.v, mom), dB_de = 2.0 * moment_sum(fb.v, fb_de.v, mom);
+    const double dC_al = moment_sum(fa_al.v, fb.v, mom) + moment_sum(fa.v, fb_al.v, mom);
+    const double dC_de = moment_sum(fa_de.v, fb.v, mom) + moment_sum(fa.v, fb_de.v, mom);
+    acc[2] += FA * dA_al + FB * dB_al + FC * dC_al;
+    acc[3] += FA * dA_de + FB * dB_de + FC * dC_de;
     const double w = gF ? gF[ci] : 1.0;
     double* o = dp + 4 * ci + threadIdx.x;
     o[0] = w * acc[0];

@@ -21,30 +21,9 @@
 // with 256 B rows (nfft = 2^20, B2 = 16) the blocked layout makes pass 2
 // 13 % faster and pass 1 6 % slower (step +3.5 %); with 512 B rows (nfft =
 // 2^19, B2 = 32) pass 2 gains 1 % and pass 1 loses 3 %.
-#include "demod.h"
-#include "fft_block.h"
-#include "internal.h"
+#include "tiles.h"
 
 namespace {
-
-template <typename T>
-constexpr int cfg_B2(int R) {
-  return sizeof(T) == 4 ? (4096 / R < 64 ? 4096 / R : 64) : (2048 / R < 32 ? 2048 / R : 32);
-}
-constexpr int cfg_block(int nb) { return nb < 64 ? 64 : (nb > 256 ? 256 : nb); }
-
-// The spill layout for pass 2 blocks of B2 columns (see above).
-template <typename T>
-constexpr bool spill_blocked(int B2) {
-  return B2 * (int)sizeof(Pair<T>) < 512;
-}
-
-// Position of spill element (r, k2) within a node's nfft elements in the
-// blocked layout; lb2 = log2(B2).  A bijection onto [0, R C) when B2 divides C.
-__device__ __forceinline__ int64_t spill_index(int r, int k2, int R, int lb2) {
-  const int B2 = 1 << lb2;
-  return ((int64_t)(k2 >> lb2) * R + r) * B2 + (k2 & (B2 - 1));
-}
 
 // Map the hardware workgroup id so that consecutive logical column blocks run
 // on the same XCD (the dispatcher deals workgroups round-robin over 8 XCDs):
@@ -59,144 +38,23 @@ __global__ void __launch_bounds__(cfg_block(C / 16))
 k_pass1(SegDev sg, const Quad<T>* __restrict__ quads, int64_t qstride, const SkyConst* __restrict__ skies,
         const NodeDev* __restrict__ nodes, const cpx<T>* __restrict__ twC, const cpx<T>* __restrict__ twlo,
         const cpx<T>* __restrict__ twhi, Pair<T>* __restrict__ spill) {
-  constexpr int BLOCK = cfg_block(C / 16);
   __shared__ lds_t<Pair<T>> lds[lds_slots(C, 1)];
-  const int r = blockIdx.x;
   const int nd = blockIdx.y;
-  const NodeDev node = nodes[nd];
-  const Quad<T>* __restrict__ col = quads + (int64_t)node.sky * qstride + (int64_t)r * sg.Ceff;
-  const double tb0 = skies[node.sky].tb0;
-  const double fdot = node.fdot;
-  const double fshift = node.fshift;
-  const int ceff = sg.Ceff;
-  const int R = sg.R;
-  const double dt = sg.dt;
-  // columns c >= ceff are the zero padding
-  auto make = [&](const Quad<T>& q, int c, int) -> Pair<T> {
-    if (c < ceff) return demod_elem<T>(q, tb0, r + R * c, dt, fdot, fshift);
-    return Pair<T>{{(T)0, (T)0}, {(T)0, (T)0}};
-  };
-  Pair<T>* __restrict__ dst = spill + (int64_t)nd * sg.nfft;
-  const int lb2 = BLK ? __builtin_ctz(cfg_B2<T>(R)) : 0;  // log2 of pass 2's B2 (BLK = spill_blocked)
-  // inter-pass twiddle e^{-2 pi i r k2/nfft} for the outputs k2 = i + q STR of a
-  // butterfly: (table value at r i) x (table value at r STR)^q
-  auto store = [&](int i, int, auto& v, auto str) {
-    constexpr int RS = std::extent<std::remove_reference_t<decltype(v)>>::value;
-    constexpr int STR = decltype(str)::value;
-    const int m0 = r * i, ms = r * STR;  // both < nfft, exact
-    const cpx<T> base = cmul(twhi[m0 >> 12], twlo[m0 & 4095]);
-    const cpx<T> step = cmul(twhi[ms >> 12], twlo[ms & 4095]);
-    cpx<T> pw[RS];
-    powers<RS>(step, pw);
-#pragma unroll
-    for (int q = 0; q < RS; ++q) {
-      const int k2 = i + q * STR;
-      int64_t at;
-      if constexpr (BLK) at = spill_index(r, k2, R, lb2);
-      else at = (int64_t)r * C + k2;
-      store_stream(&dst[at], twmul(v[q], cmul(base, pw[q])));
-    }
-  };
-  if constexpr (C >= 1024) {
-    // all sky-record reads of a thread in flight together (the interbinned
-    // 2-day grid: pass 1 ~20 % faster); the reads of padding columns are
-    // clamped to the row's last record (ceff >= 1)
-    auto read = [&](int c, int) -> Quad<T> { return col[c < ceff ? c : ceff - 1]; };
-    block_fft_split<Pair<T>, C, 1, BLOCK, -1>(lds, twC, read, make, store);
-  } else {
-    // short rows: one read per element; the split form would double the
-    // registers of these 64-thread workgroups
-    auto load = [&](int c, int) -> Pair<T> {
-      return c < ceff ? make(col[c], c, 0) : Pair<T>{{(T)0, (T)0}, {(T)0, (T)0}};
-    };
-    block_fft<Pair<T>, C, 1, BLOCK, -1>(lds, twC, load, store);
-  }
+  pass1_tile<T, C, BLK>(sg, quads, qstride, skies, nodes[nd], blockIdx.x, twC, twlo, twhi,
+                        spill + (int64_t)nd * sg.nfft, lds);
 }
 
-// Pass 2 for the column block cb (B2 adjacent k2) of node nd.
 template <typename T, int R, int MODE>
 __global__ void __launch_bounds__(cfg_block(cfg_B2<T>(R) * R / 16))
 k_pass2(SegDev sg, const Pair<T>* __restrict__ spill, const NodeDev* __restrict__ nodes,
         const SkyCoef* __restrict__ coef, const cpx<T>* __restrict__ twR, GridOut out,
         MaxPartial* __restrict__ part) {
   constexpr int B2 = cfg_B2<T>(R);
-  constexpr int BLOCK = cfg_block(B2 * R / 16);
   __shared__ lds_t<Pair<T>> lds[lds_slots(R, B2)];
   const int nd = blockIdx.y;
-  const int cb = xcd_local(blockIdx.x, gridDim.x);
   const NodeDev node = nodes[nd];
-  const int C = sg.C;
-  // blocked: the workgroup's R x B2 elements are contiguous; row-major: rows
-  // of B2 elements at stride C
-  constexpr bool BLK = spill_blocked<T>(B2);
-  const Pair<T>* __restrict__ src = spill + (int64_t)nd * sg.nfft + (BLK ? (int64_t)cb * R * B2 : (int64_t)cb * B2);
-  auto load = [&](int r, int col) -> Pair<T> {
-    if constexpr (BLK) return load_stream(&src[r * B2 + col]);
-    else return load_stream(&src[(int64_t)r * C + col]);
-  };
-  const SkyCoef cf = coef[node.sky];
-  const T cB = (T)cf.cB, cA = (T)cf.cA, cC = (T)cf.cC;
-  const int64_t klo = out.k_lo, khi = out.k_hi;
-  double best = -1.0;
-  int64_t bestk = INT64_MAX;
-  auto store1 = [&](int k1, int col, const Pair<T>& v) {
-    if (k1 >= R / 2) return;
-    const int64_t k = (int64_t)C * k1 + (int64_t)cb * B2 + col;
-    if (k < klo || k >= khi) return;
-    // explicit fused operations: every output mode rounds identically
-    const T pa = fma(v.a.x, v.a.x, v.a.y * v.a.y);
-    const T pb = fma(v.b.x, v.b.x, v.b.y * v.b.y);
-    const T re = fma(v.a.x, v.b.x, v.a.y * v.b.y);
-    const T F = fma(cB, pa, fma(cA, pb, -(cC * re)));
-    if constexpr (MODE == 0) {
-      store_stream(&((T*)out.F)[(int64_t)node.row * (khi - klo) + (k - klo)], F);
-    } else if constexpr (MODE == 1) {
-      const double f = (double)F;
-      if (f > best || (f == best && k < bestk)) {
-        best = f;
-        bestk = k;
-      }
-    } else {
-      if ((double)F > out.threshold) {
-        const unsigned long long i = atomicAdd(out.n_xing, 1ull);
-        if ((int64_t)i < out.max_xing) ((Crossing*)out.xing)[i] = Crossing{node.row, k, (double)F};
-      }
-    }
-  };
-  auto store = [&](int i, int col, auto& v, auto str) {
-    constexpr int RS = std::extent<std::remove_reference_t<decltype(v)>>::value;
-    constexpr int STR = decltype(str)::value;
-#pragma unroll
-    for (int q = 0; q < RS; ++q) store1(i + q * STR, col, v[q]);
-  };
-  block_fft<Pair<T>, R, B2, BLOCK, -1>(lds, twR, load, store);
-  if constexpr (MODE == 1) {
-    // block arg-max, ties to the lowest bin
-    __shared__ double sf[BLOCK / 64];
-    __shared__ int64_t sk[BLOCK / 64];
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-      const double f2 = __shfl_down(best, o, 64);
-      const int64_t k2 = __shfl_down(bestk, o, 64);
-      if (f2 > best || (f2 == best && k2 < bestk)) {
-        best = f2;
-        bestk = k2;
-      }
-    }
-    if ((threadIdx.x & 63) == 0) {
-      sf[threadIdx.x >> 6] = best;
-      sk[threadIdx.x >> 6] = bestk;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      for (int w = 1; w < BLOCK / 64; ++w)
-        if (sf[w] > best || (sf[w] == best && sk[w] < bestk)) {
-          best = sf[w];
-          bestk = sk[w];
-        }
-      part[(int64_t)nd * gridDim.x + cb] = MaxPartial{best, bestk};
-    }
-  }
+  pass2_tile<T, R, MODE>(sg, spill + (int64_t)nd * sg.nfft, node, coef[node.sky], twR, out,
+                         xcd_local(blockIdx.x, gridDim.x), part + (int64_t)nd * gridDim.x, lds);
 }
 
 constexpr int cmax(int a, int b) { return a > b ? a : b; }

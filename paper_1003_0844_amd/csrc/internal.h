@@ -76,6 +76,56 @@ struct MaxPartial {
   int64_t k;
 };
 
+// ---- the persistent grid launch (persist.hip) ----
+// The work of a whole grid call as one queue of tiles, each one workgroup's
+// share of a stage: the sky preparation of a batch of sky positions
+// (set-up, record tiles, combination coefficients), pass 1 of a node (its R
+// columns), pass 2 of a node (its C/B2 = R column blocks at C = 4096).  The
+// queue is cut into units of PUNIT consecutive tiles of one stage; a unit
+// record says which.
+constexpr int PUNIT = 64;
+constexpr int PREP_POS = 4;  // sample positions per thread of a sky-preparation tile
+enum : int32_t { PU_SKY = 0, PU_P1 = 1, PU_P2 = 2 };
+struct PUnit {
+  int32_t kind;  // PU_SKY / PU_P1 / PU_P2
+  int32_t id;    // batch (PU_SKY) or node (PU_P1, PU_P2) of the call
+  int32_t sub;   // the unit's place in its stage: tile = sub * PUNIT + item % PUNIT
+  int32_t pad;
+};
+// A batch of sky positions of one segment and the nodes that use them.
+struct PBatch {
+  int32_t seg, set;      // segment; sky set (0 / 1) that holds its records
+  int32_t sky0, nsky;    // into the call's (alpha, delta) list
+  int32_t node0, nnode;  // into the call's node list
+  int32_t nblk;          // sample blocks of PREP_POS x 256 positions
+  int32_t nprep;         // record tiles: ceil(nsky / SKY_GROUP) x nblk
+};
+struct PSegTw {  // twiddle tables of a segment
+  const void *twC, *twR, *twlo, *twhi;
+};
+struct PersistArgs {
+  const SegDev* segs;
+  const PSegTw* tw;
+  const PUnit* units;
+  int64_t nitems;             // tiles in the queue (units x PUNIT)
+  const PBatch* batches;
+  int32_t nbatch, nslots;     // batches; spill slots
+  const int32_t* node_batch;  // batch of each node
+  const NodeDev* nodes;       // the call's nodes, grouped by batch
+  const double* sky_ad;       // (alpha, delta) of the call's sky positions
+  void* quads[2];             // sky sets: records of up to 64 skies, stride R Ceff of the batch's segment
+  SkyConst* sky[2];
+  SkyCoef* coef[2];
+  void* spill;                // nslots x slot_elems spill elements; node n uses slot n % nslots
+  int64_t slot_elems;
+  MaxPartial* part;           // nslots x 1024 max partials
+  GridOut out;
+  unsigned long long* head;   // tiles claimed
+  uint32_t* cnt;              // completion counters: 4 per batch, then 3 per node
+  uint32_t* error;            // sticky flag: a wait outlived spin_ticks
+  uint64_t spin_ticks;        // wall-clock ticks a wait may last
+};
+
 constexpr double SPAN_EPS = 1e-6;  // margin of the data-span test, in samples
 constexpr int FSTATE = 8;  // doubles of forward state per candidate: S_a, S_b, A, B, C, pad
 
@@ -104,6 +154,12 @@ hipError_t grid_pass2(int prec, int R, const SegDev& seg, const void* d_spill, c
 hipError_t max_finalize(const MaxPartial* d_part, int nparts, const NodeDev* d_nodes, int nnodes, int prec,
                         const GridOut& out, hipStream_t st);
 hipError_t zero_u64(unsigned long long* p, hipStream_t st);
+// persist.hip: the whole grid call in one launch (FP32, C = 4096, 64 <= R <=
+// 1024, no interbinning); counters, head and spill must be zeroed / sized by
+// the caller (persist_zero clears counters and head)
+int persistent_blocks(int mode);
+hipError_t persist_zero(uint32_t* cnt, int64_t n32, unsigned long long* head, hipStream_t st);
+hipError_t grid_persistent(const PersistArgs& a, int mode, int blocks, hipStream_t st);
 // prep.hip
 hipError_t make_twiddles(int prec, int64_t denom, int64_t count, int64_t step, void* d_tab, hipStream_t st);
 hipError_t fft_c2c_f64(cpx<double>* d_data, int64_t L, int dir, cpx<double>* d_tmp, cpx<double>* d_twtab,

@@ -22,11 +22,17 @@ __device__ double block_F(const SegDev& sg, const Cand& c, double* sh, double* s
   SkyConst k;
   setup_sky(sg, c, k);
   double acc[7] = {0, 0, 0, 0, 0, 0, 0};
-  for (int64_t j = threadIdx.x; j < sg.n; j += GB) {
-    if constexpr (EXACT) exact_terms(sg, k, c, j, acc);
-    else method_terms(sg, k, c, j, acc);
+  if constexpr (EXACT) {
+    for (int64_t j = threadIdx.x; j < sg.n; j += GB) exact_terms(sg, k, c, j, acc);
+    block_sums<7>(acc, sh);
+  } else {
+    double acc4[4] = {0, 0, 0, 0};
+    for (int64_t j = threadIdx.x; j < sg.n; j += GB) method_terms(sg, k, c, j, acc4);
+    block_sums<4>(acc4, sh);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) acc[i] = acc4[i];
+    if (threadIdx.x == 0) abc_moments(sg, k, acc[4], acc[5], acc[6]);
   }
-  block_sums<7>(acc, sh);
   if (threadIdx.x == 0) *shF = combine_F(acc, sg.sigma2);
   __syncthreads();
   const double F = *shF;

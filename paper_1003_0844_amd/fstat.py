@@ -77,7 +77,7 @@ class _Segment(ctypes.Structure):
 
 class _Options(ctypes.Structure):
     _fields_ = [("interp", ctypes.c_int32), ("prec", ctypes.c_int32), ("device", ctypes.c_int32),
-                ("max_batch", ctypes.c_int32), ("autotune", ctypes.c_int32)]
+                ("max_batch", ctypes.c_int32), ("autotune", ctypes.c_int32), ("launch", ctypes.c_int32)]
 
 
 class _Out(ctypes.Structure):
@@ -101,9 +101,10 @@ EXPORTS = ("fstat_plan", "fstat_grid", "fstat_graph_create", "fstat_graph_launch
            "fstat_lattice_fisher", "fstat_lattice_build", "fstat_lattice_segment", "fstat_lattice_nodes",
            "fstat_copy_probe", "fstat_bin_params",
            "fstat_profile",
-           "fstat_profile_read", "fstat_plan_schedule", "fstat_destroy", "fstat_strerror")
+           "fstat_profile_read", "fstat_plan_schedule", "fstat_plan_status", "fstat_destroy", "fstat_strerror")
 K_SKY, K_PASS1, K_PASS2, K_OTHER = 0, 1, 2, 3
 NU_DEEP_HOLES, NU_COVERING = 0, 1
+LAUNCH_PASSES, LAUNCH_PERSISTENT = 0, 1
 
 _lib = None
 
@@ -140,6 +141,7 @@ def lib():
         L.fstat_plan_info.argtypes = [vp, i32, P(i64), P(i64), P(ctypes.c_double), P(i32), P(i32)]
         L.fstat_demod_series.argtypes = [vp, vp, vp, vp]
         L.fstat_profile.argtypes = [vp, i32]
+        L.fstat_plan_status.argtypes = [vp]
         L.fstat_plan_schedule.argtypes = [vp, i32, P(i32), P(i32), P(i32), P(i32), P(i32)]
         L.fstat_profile_read.argtypes = [vp, i32, P(i64), P(ctypes.c_double), P(ctypes.c_double)]
         L.fstat_destroy.argtypes = [vp]
@@ -151,7 +153,8 @@ def lib():
                      "fstat_lattice_build", "fstat_lattice_segment", "fstat_lattice_nodes", "fstat_copy_probe",
                      "fstat_bin_params",
                      "fstat_eval", "fstat_adjoint", "fstat_grad", "fstat_grad_static", "fstat_plan_info",
-                     "fstat_demod_series", "fstat_profile", "fstat_profile_read", "fstat_plan_schedule"):
+                     "fstat_demod_series", "fstat_profile", "fstat_profile_read", "fstat_plan_schedule",
+                     "fstat_plan_status"):
             getattr(L, name).restype = i32
         _lib = L
     return _lib
@@ -350,7 +353,7 @@ class Plan:
 
     def __init__(self, segments: Sequence[SegmentSpec], det: Detector, eph: Ephemeris,
                  interp: int = LINEAR_UP2, prec: int = FP32, device: int = 0, max_batch: int = 0,
-                 autotune: bool = False):
+                 autotune: bool = False, launch: int = 0):
         L = lib()
         self._keep = []
         segs = (_Segment * len(segments))()
@@ -358,7 +361,7 @@ class Plan:
             segs[i] = _segment_struct(s, self._keep)
         d = _Detector(det.lat, det.lon, det.gamma, det.zeta, det.radius)
         e = _eph_struct(eph)
-        o = _Options(interp, prec, device, max_batch, 1 if autotune else 0)
+        o = _Options(interp, prec, device, max_batch, 1 if autotune else 0, int(launch))
         h = ctypes.c_void_p()
         _check(L.fstat_plan(segs, len(segments), ctypes.byref(d), ctypes.byref(e), ctypes.byref(o),
                             ctypes.byref(h)), "fstat_plan")
@@ -383,6 +386,11 @@ class Plan:
     @property
     def handle(self):
         return self._h
+
+    def status(self) -> None:
+        """fstat_plan_status: waits for the device; raises FStatError if a
+        persistent launch of this plan stopped early since the last check."""
+        _check(lib().fstat_plan_status(self._h), "fstat_plan_status")
 
     def info(self, seg: int = 0) -> dict:
         n, nfft = ctypes.c_int64(), ctypes.c_int64()

@@ -46,7 +46,7 @@ def _plan_status(n=43082, dt=2.0, days=1, nfft=0, interp=1, prec=0, x=None, det=
     dd = fstat._Detector(d.lat, d.lon, d.gamma, d.zeta, d.radius)
     e = fstat.Ephemeris()
     ee = fstat._Ephemeris(e.obliquity, e.orbit_radius, e.orbit_omega, e.orbit_phase0, e.sidereal_day, e.gmst0)
-    o = fstat._Options(interp, prec, 0, 0, 0)
+    o = fstat._Options(interp, prec, 0, 0, 0, 0)
     h = ctypes.c_void_p()
     return L.fstat_plan(ctypes.byref(seg), 1, ctypes.byref(dd), ctypes.byref(ee), ctypes.byref(o), ctypes.byref(h))
 
@@ -93,6 +93,7 @@ def test_calls_on_null_plan_are_rejected():
     params = np.zeros((1, 4))
     assert L.fstat_bin_params(None, nodes.ctypes.data_as(ctypes.c_void_p), k.ctypes.data_as(ctypes.c_void_p), 1, 0,
                               params.ctypes.data_as(ctypes.c_void_p), None) == fstat.EINVAL
+    assert L.fstat_plan_status(None) == fstat.EINVAL
     L.fstat_graph_destroy(None)
     L.fstat_destroy(None)
 

@@ -27,9 +27,9 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, GB/s
 FP64_PEAK_GFLOPS = 78600.0   # MI355X vector FP64
 PROFILES = os.path.join(ROOT, "profiles")
 # sources that compile into the two FFT-pass kernels
-KERNEL_SOURCES = ("grid.hip", "fft_block.h", "cplx.h", "demod.h", "geometry.h", "internal.h")
+KERNEL_SOURCES = ("grid.hip", "tiles.h", "moments.h", "fft_block.h", "cplx.h", "demod.h", "geometry.h", "internal.h")
 # sources of the refinement kernels (F and its adjoint at continuous parameters)
-GRAD_SOURCES = ("grad.hip", "candidate.h", "demod.h", "geometry.h", "internal.h")
+GRAD_SOURCES = ("grad.hip", "candidate.h", "moments.h", "cplx.h", "demod.h", "geometry.h", "internal.h")
 
 
 def parse():
@@ -55,6 +55,9 @@ def parse():
                     help="short run for hardware-counter collection: one grid call on two node batches "
                          "of the benchmark's (autotuned) schedule "
                          "and a 1 GiB device copy of known size (the calibration of the byte counters)")
+    ap.add_argument("--refine-counters", action="store_true",
+                    help="short run for FP64 instruction counters: one F + gradient call (fstat_grad) on the "
+                         "4096 refinement candidates")
     return ap.parse_args()
 
 
@@ -383,7 +386,7 @@ def large6d_leg():
     return res
 
 
-def refine_leg():
+def refine_leg(reps=5):
     """4096 candidates half a cell (per parameter) from a point of the 1-day
     workload (N = 43082, dt = 2 s, LINEAR_UP2): F and dF/d(f, fdot, alpha,
     delta) in FP64 (fstat_grad: forward kernel, then the adjoint)."""
@@ -401,7 +404,11 @@ def refine_leg():
     P = torch.tensor(np.array([sig["f"], sig["fdot"], sig["alpha"], sig["delta"]])
                      + 0.5 * cell * synth.candidate_offsets(1003, 4096), dtype=torch.float64, device="cuda")
     plan.grad(P)
-    s = _median_time(lambda: plan.grad(P), 5)
+    torch.cuda.synchronize()
+    if reps <= 1:
+        log("refinement counters run: one warm-up call and this one, 4096 candidates")
+        return None
+    s = _median_time(lambda: plan.grad(P), reps)
     res = {"workload": "4096 candidates at +-1/2 cell around a 1-day point (N=43082, dt=2 s), LINEAR_UP2, FP64",
            "value": round(4096 / s, 1), "unit": "candidates/s", "s_per_call": round(s, 5)}
     flops = flop_record("k_eval+k_adjoint", w.n)
@@ -422,6 +429,9 @@ def main():
         sys.exit(2)
     if args.counters:
         counters_run(args)
+        return
+    if args.refine_counters:
+        refine_leg(reps=1)
         return
     import numpy as np
     import torch

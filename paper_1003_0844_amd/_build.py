@@ -33,33 +33,68 @@ def common_flags():
             "-I" + os.path.join(ROOT, "include"), "-I" + CSRC]
 
 
-def build_library(verbose: bool = False) -> str:
-    os.makedirs(os.path.join(HERE, "_objs"), exist_ok=True)
+# Host-side AddressSanitizer + UndefinedBehaviorSanitizer instrumentation (the
+# device code is built as usual): a CPU-only check of the library's host code.
+SANITIZE_HOST = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                 "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-fno-sanitize-recover=all"]
+
+
+def _clangxx() -> str:
+    return os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "lib", "llvm", "bin", "clang++")
+
+
+def build_library(verbose: bool = False, sanitize: bool = False, out: str = "") -> str:
+    """Compile every source into LIB (or `out`).  sanitize: instrument the host
+    code with AddressSanitizer and UndefinedBehaviorSanitizer (loading the
+    result needs the sanitizer runtime preloaded)."""
+    objdir = os.path.join(HERE, "_objs_san" if sanitize else "_objs")
+    os.makedirs(objdir, exist_ok=True)
     hipcc = _hipcc()
+    lib = out or LIB
 
     def compile_one(src):
-        obj = os.path.join(HERE, "_objs", os.path.splitext(src)[0] + ".o")
+        obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
         if src.endswith(".cpp"):   # host-only C++
-            cmd = [hipcc, "-x", "c++", "-O3", "-std=c++17", "-fPIC", "-I" + os.path.join(ROOT, "include"),
-                   "-I" + CSRC, "-c", os.path.join(CSRC, src), "-o", obj]
+            cc = _clangxx() if sanitize else hipcc
+            cmd = [cc, "-x", "c++", "-O3" if not sanitize else "-O1", "-std=c++17", "-fPIC",
+                   "-I" + os.path.join(ROOT, "include"), "-I" + CSRC, "-c", os.path.join(CSRC, src), "-o", obj]
+            if sanitize:
+                cmd[1:1] = [f.replace("-Xarch_host", "") for f in SANITIZE_HOST if f != "-Xarch_host"]
         else:
-            cmd = [hipcc, *common_flags(), "-c", os.path.join(CSRC, src), "-o", obj]
+            cmd = [hipcc, *common_flags(), *(SANITIZE_HOST if sanitize else []), "-c", os.path.join(CSRC, src),
+                   "-o", obj]
         r = subprocess.run(cmd, capture_output=True, text=True)
         if r.returncode != 0:
-            raise RuntimeError("hipcc failed for %s:\n%s" % (src, r.stderr[-6000:]))
+            raise RuntimeError("compile failed for %s:\n%s" % (src, r.stderr[-6000:]))
         if verbose and r.stderr.strip():
             print(r.stderr)
         return obj
 
     with ThreadPoolExecutor(max_workers=min(len(SOURCES), 8)) as ex:
         objs = list(ex.map(compile_one, SOURCES))
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc, "--offload-arch=" + ARCH, "-shared", "-fPIC", *objs, "-o", tmp]
+    tmp = lib + ".tmp%d" % os.getpid()
+    if sanitize:
+        rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
+        cmd = [_clangxx(), "-shared", "-fPIC", "-shared-libasan", "-fsanitize=address,undefined", *objs,
+               "-L" + os.path.join(rocm, "lib"), "-lamdhip64", "-Wl,-rpath," + os.path.join(rocm, "lib"), "-o", tmp]
+    else:
+        cmd = [hipcc, "--offload-arch=" + ARCH, "-shared", "-fPIC", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed:\n" + r.stderr[-4000:])
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
+
+
+def sanitizer_runtime() -> str:
+    """The AddressSanitizer runtime of the ROCm clang (to preload)."""
+    import glob
+    rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
+    hits = sorted(glob.glob(os.path.join(rocm, "lib", "llvm", "lib", "clang", "*", "lib", "linux",
+                                         "libclang_rt.asan-x86_64.so")))
+    if not hits:
+        raise RuntimeError("no libclang_rt.asan-x86_64.so under " + rocm)
+    return hits[-1]
 
 
 if __name__ == "__main__":

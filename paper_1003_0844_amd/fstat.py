@@ -17,7 +17,9 @@ import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libfstat.so")
+# FSTAT_LIBRARY names another build of the same library (e.g. the host
+# sanitizer build of _build.build_library(sanitize=True)); default: in-tree.
+LIB_PATH = os.environ.get("FSTAT_LIBRARY") or os.path.join(_HERE, "libfstat.so")
 
 NEAREST, LINEAR_UP2, CUBIC_UP2 = 0, 1, 2
 FP32, FP64 = 0, 1

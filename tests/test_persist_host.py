@@ -2,11 +2,15 @@
 (csrc/persist_sched.h) of a three-segment call is checked to be in dependency
 order, and a threaded emulation of the kernel's claim / wait / signal logic
 runs every tile exactly once, for several workgroup counts and spill-slot
-counts (no GPU; the kernel itself is switched off in the library)."""
+counts (no GPU; the kernel itself is switched off in the library).  The
+emulation is built with the host sanitizers (AddressSanitizer,
+UndefinedBehaviorSanitizer) over the schedule code."""
 import os
 import subprocess
 
 import pytest
+
+from paper_1003_0844_amd import _build
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -15,7 +19,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def emu(tmp_path_factory):
     exe = str(tmp_path_factory.mktemp("emu") / "persist_queue_emu")
     hipcc = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "bin", "hipcc")
-    cmd = [hipcc, "-O2", "-std=c++17", "-I" + os.path.join(ROOT, "include"),
+    cmd = [hipcc, "-O1", "-std=c++17", *_build.SANITIZE_HOST, "-I" + os.path.join(ROOT, "include"),
            "-I" + os.path.join(ROOT, "paper_1003_0844_amd", "csrc"), os.path.join(ROOT, "tests", "persist_queue_emu.hip"),
            "-o", exe, "-lpthread"]
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -136,10 +136,9 @@ typedef struct {
                                       C = 4096 columns) and no interbinning; other calls run as
                                       FSTAT_LAUNCH_PASSES.  Every wait inside the kernel is
                                       bounded: if one expires the kernel stops early and the
-                                      plan's error flag is set (fstat_plan_status).
-                                      Currently switched off: a plan created with it runs
-                                      every call as FSTAT_LAUNCH_PASSES (its kernel did not
-                                      finish on its first GPU run; the cause is not known). */
+                                      plan's error flag is set (fstat_plan_status).  The
+                                      outputs equal those of FSTAT_LAUNCH_PASSES bit for bit
+                                      (the same tile code runs in both). */
 /* Environment: FSTAT_STREAMS=1 (or 2) at plan creation fixes the stream mode
  * of every segment (see fstat_plan_schedule) instead of the default or tuned
  * one; meant for per-kernel timing. */

@@ -27,8 +27,13 @@ def _hipcc() -> str:
     return "hipcc"
 
 
+# -ffp-contract=on: a multiply and an add are fused only within one source
+# expression, so that the rounding of the shared tile code does not depend on
+# the kernel it is inlined into (the persistent launch and the pass kernels
+# give bit-identical maps); across statements the default would fuse as the
+# surrounding code allows.
 def common_flags():
-    return ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
+    return ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-ffp-contract=on",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
             "-I" + os.path.join(ROOT, "include"), "-I" + CSRC]
 

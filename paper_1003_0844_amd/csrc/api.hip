@@ -602,10 +602,8 @@ bool persistent_split(const fstat_plan_s* p, int64_t nfft) {
 // ---------------------------------------------------------------------------
 // Calls the persistent kernel runs: FP32, no interbinning, every segment of
 // the call split with C = 4096 (64 <= R <= 1024).
-// The persistent kernel is switched off: its first run on the GPU did not
-// finish (no output for minutes) and the cause is not known; every call runs
-// as passes until it is.  kPersistentEnabled gates the dispatch.
-constexpr bool kPersistentEnabled = false;
+// kPersistentEnabled gates the dispatch (false: every call runs as passes).
+constexpr bool kPersistentEnabled = true;
 
 bool persistent_call(const fstat_plan_s* p, const fstat_node* nodes, int64_t n_nodes, const fstat_out* out) {
   if (!kPersistentEnabled) return false;

@@ -66,13 +66,24 @@ __device__ bool wait_ge(const PersistArgs& a, const uint32_t* c, uint32_t target
 }
 
 // Publish one completion (one thread, after a workgroup barrier): everything
-// the workgroup wrote becomes visible to the acquirers of *c.
-__device__ __forceinline__ void signal(uint32_t* c, uint32_t v = 1u) {
+// the workgroup wrote becomes visible to the acquirers of *c.  The explicit
+// wait after the fence keeps the L2 write-back complete before the count: at
+// the head of the claim loop, with the previous tile's stores still in flight
+// on the back edge, the compiler omits the wait the fence implies.
+__device__ __forceinline__ void release_agent() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __builtin_amdgcn_s_waitcnt(0);
+}
+__device__ __forceinline__ void signal(uint32_t* c, uint32_t v = 1u) {
+  release_agent();
   __hip_atomic_fetch_add(c, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ __forceinline__ void acquire() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
+
+// A flag that thread 0 left in LDS, read as a wave-uniform value: the branch
+// on it is a scalar branch, so every lane of a wave takes it together.
+__device__ __forceinline__ bool uniform_flag(const int& v) { return __builtin_amdgcn_readfirstlane(v) != 0; }
 
 __device__ __forceinline__ int64_t uniform64(int64_t v) {
   const int lo = __builtin_amdgcn_readfirstlane((int)(uint32_t)v);
@@ -124,8 +135,26 @@ __global__ void __launch_bounds__(PB, 3) k_persist(PersistArgs a) {
   __shared__ unsigned long long s_item;
   __shared__ int s_ok, s_last;
   const int tid = threadIdx.x;
+  // Control flow: every branch that decides which barrier a thread reaches next
+  // is taken on a wave-uniform value (the claimed item, or a flag thread 0 left
+  // in LDS, read with readfirstlane), and every thread-0 block is followed by a
+  // barrier before such a branch.  With a thread-0 block in front of the loop
+  // latch (a completion signalled at the end of a tile) and another behind it
+  // (the claim), the compiler may merge the two tests of tid == 0 and send
+  // threads 1.. straight back to the barrier after the claim while thread 0's
+  // lane waits outside that inner loop: the workgroup would run the same tile
+  // over and over and never claim another.  So a tile's completion is counted
+  // by thread 0 in the block that claims the next tile (or after the loop):
+  // pend_rel / pend_add name the counters, set alike in every thread.
+  uint32_t* pend_rel = nullptr;  // published with a release
+  uint32_t* pend_add = nullptr;  // counted without one (a count the host schedule only reads in order)
   for (;;) {
-    if (tid == 0) s_item = atomicAdd(a.head, 1ull);
+    if (tid == 0) {
+      if (pend_rel) signal(pend_rel);
+      if (pend_add) __hip_atomic_fetch_add(pend_add, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      s_item = atomicAdd(a.head, 1ull);
+    }
+    pend_rel = pend_add = nullptr;
     __syncthreads();
     const int64_t item = uniform64((int64_t)s_item);
     if (item >= a.nitems) break;
@@ -152,7 +181,7 @@ __global__ void __launch_bounds__(PB, 3) k_persist(PersistArgs a) {
         s_ok = ok;
       }
       __syncthreads();
-      if (!s_ok) break;
+      if (!uniform_flag(s_ok)) break;
       if (tile == 0) {
         if (tid < bt.nsky)
           a.sky[bt.set][tid] = sky_setup_one(a.sky_ad[2 * (bt.sky0 + tid)], a.sky_ad[2 * (bt.sky0 + tid) + 1], sg.geo);
@@ -162,7 +191,7 @@ __global__ void __launch_bounds__(PB, 3) k_persist(PersistArgs a) {
         if (tid < bt.nsky) a.coef[bt.set][tid] = sky_coef_one(a.sky[bt.set][tid], sg.mom, sg.sigma2);
       }
       __syncthreads();
-      if (tid == 0) signal(batch_cnt(a, b, tile == 0 ? 0 : (tile <= bt.nprep ? 1 : 2)));
+      pend_rel = batch_cnt(a, b, tile == 0 ? 0 : (tile <= bt.nprep ? 1 : 2));
       continue;
     }
 
@@ -183,11 +212,11 @@ __global__ void __launch_bounds__(PB, 3) k_persist(PersistArgs a) {
         s_ok = ok;
       }
       __syncthreads();
-      if (!s_ok) break;
+      if (!uniform_flag(s_ok)) break;
       if (R > 128) pass1_of<true>(sg, a, tw, bt, n, tile, lds);  // the spill layout of pass 2's B2
       else pass1_of<false>(sg, a, tw, bt, n, tile, lds);
       __syncthreads();
-      if (tid == 0) signal(node_cnt(a, n, 0));
+      pend_rel = node_cnt(a, n, 0);
       continue;
     }
 
@@ -199,7 +228,7 @@ __global__ void __launch_bounds__(PB, 3) k_persist(PersistArgs a) {
       s_ok = ok;
     }
     __syncthreads();
-    if (!s_ok) break;
+    if (!uniform_flag(s_ok)) break;
     switch (R) {
       case 64: pass2_of<64, MODE>(sg, a, tw, bt, n, tile, lds); break;
       case 128: pass2_of<128, MODE>(sg, a, tw, bt, n, tile, lds); break;
@@ -211,13 +240,13 @@ __global__ void __launch_bounds__(PB, 3) k_persist(PersistArgs a) {
     if constexpr (MODE == 1) {
       // the last column block of the node to arrive reduces its partials
       if (tid == 0) {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        release_agent();
         const uint32_t old = __hip_atomic_fetch_add(node_cnt(a, n, 1), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         s_last = old + 1u == (uint32_t)R;
         if (s_last) acquire();
       }
       __syncthreads();
-      if (s_last && tid < 64) {
+      if (uniform_flag(s_last) && tid < 64) {
         const MaxPartial* p = a.part + (int64_t)(n % a.nslots) * 1024;
         double best = -1.0;
         int64_t bk = INT64_MAX;
@@ -237,10 +266,13 @@ __global__ void __launch_bounds__(PB, 3) k_persist(PersistArgs a) {
       }
       __syncthreads();
     }
-    if (tid == 0) {
-      signal(node_cnt(a, n, 2));
-      __hip_atomic_fetch_add(batch_cnt(a, b, 3), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
+    pend_rel = node_cnt(a, n, 2);
+    pend_add = batch_cnt(a, b, 3);
+  }
+  // the last tile's completion (the loop ends at the claim after it, or on an error)
+  if (tid == 0) {
+    if (pend_rel) signal(pend_rel);
+    if (pend_add) __hip_atomic_fetch_add(pend_add, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 

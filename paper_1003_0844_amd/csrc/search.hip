@@ -17,6 +17,21 @@ namespace {
 constexpr int NP = 4;         // parameters
 constexpr int NV = NP + 1;    // simplex vertices
 
+// A double that thread 0 left in LDS, read as a wave-uniform value.  Every
+// thread then takes the same branches of the simplex logic, and the compiler
+// sees those branches (and the loops around the block-wide sums, with their
+// barriers) as uniform.
+__device__ __forceinline__ double uniform_f64(double v) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)u);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(u >> 32));
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// A decision of the simplex logic, taken as a wave-uniform branch: every
+// thread holds the same values, so the first lane's outcome is every lane's.
+__device__ __forceinline__ bool uniform_if(bool c) { return __builtin_amdgcn_readfirstlane((int)c) != 0; }
+
 template <bool EXACT>
 __device__ double block_F(const SegDev& sg, const Cand& c, double* sh, double* shF) {
   SkyConst k;
@@ -35,7 +50,7 @@ __device__ double block_F(const SegDev& sg, const Cand& c, double* sh, double* s
   }
   if (threadIdx.x == 0) *shF = combine_F(acc, sg.sigma2);
   __syncthreads();
-  const double F = *shF;
+  const double F = uniform_f64(*shF);
   __syncthreads();  // every thread has read shF and sh before the next evaluation writes them
   return F;
 }
@@ -95,23 +110,30 @@ k_nelder_mead(const SegDev* __restrict__ segs, int nseg, const int32_t* __restri
     for (int d = 0; d < NP; ++d) v[i][d] = (i == d + 1) ? 1.0 : 0.0;
     g[i] = g_at(v[i]);
   }
-  while (nev < o.max_evals) {
-    // order the vertices by g (insertion sort, ties keep their order)
+  while (uniform_if(nev < o.max_evals)) {
+    // order the vertices by g (insertion sort, ties keep their order), with
+    // every compare-exchange spelled out: once vertex i has settled, the
+    // remaining comparisons below it find the prefix ordered and swap nothing,
+    // and the fixed indices keep v and g in registers
+#pragma unroll
     for (int i = 1; i < NV; ++i)
-      for (int j = i; j > 0 && g[j] < g[j - 1]; --j) {
-        const double tg = g[j];
-        g[j] = g[j - 1];
-        g[j - 1] = tg;
-        for (int d = 0; d < NP; ++d) {
-          const double tv = v[j][d];
-          v[j][d] = v[j - 1][d];
-          v[j - 1][d] = tv;
+#pragma unroll
+      for (int j = i; j > 0; --j)
+        if (uniform_if(g[j] < g[j - 1])) {
+          const double tg = g[j];
+          g[j] = g[j - 1];
+          g[j - 1] = tg;
+#pragma unroll
+          for (int d = 0; d < NP; ++d) {
+            const double tv = v[j][d];
+            v[j][d] = v[j - 1][d];
+            v[j - 1][d] = tv;
+          }
         }
-      }
     double diam = 0.0;
     for (int i = 1; i < NV; ++i)
       for (int d = 0; d < NP; ++d) diam = fmax(diam, fabs(v[i][d] - v[0][d]));
-    if (diam < o.tol) break;
+    if (uniform_if(diam < o.tol)) break;
     double cen[NP];
     for (int d = 0; d < NP; ++d) {
       double sum = 0.0;
@@ -122,25 +144,25 @@ k_nelder_mead(const SegDev* __restrict__ segs, int nseg, const int32_t* __restri
     for (int d = 0; d < NP; ++d) xr[d] = cen[d] + (cen[d] - v[NV - 1][d]);
     const double gr = g_at(xr);
     bool shrink = false;
-    if (gr < g[0]) {
+    if (uniform_if(gr < g[0])) {
       double xe[NP];
       for (int d = 0; d < NP; ++d) xe[d] = cen[d] + 2.0 * (xr[d] - cen[d]);
       const double ge = g_at(xe);
-      if (ge < gr) {
+      if (uniform_if(ge < gr)) {
         for (int d = 0; d < NP; ++d) v[NV - 1][d] = xe[d];
         g[NV - 1] = ge;
       } else {
         for (int d = 0; d < NP; ++d) v[NV - 1][d] = xr[d];
         g[NV - 1] = gr;
       }
-    } else if (gr < g[NV - 2]) {
+    } else if (uniform_if(gr < g[NV - 2])) {
       for (int d = 0; d < NP; ++d) v[NV - 1][d] = xr[d];
       g[NV - 1] = gr;
-    } else if (gr < g[NV - 1]) {
+    } else if (uniform_if(gr < g[NV - 1])) {
       double xc[NP];  // outside contraction
       for (int d = 0; d < NP; ++d) xc[d] = cen[d] + 0.5 * (xr[d] - cen[d]);
       const double gc = g_at(xc);
-      if (gc <= gr) {
+      if (uniform_if(gc <= gr)) {
         for (int d = 0; d < NP; ++d) v[NV - 1][d] = xc[d];
         g[NV - 1] = gc;
       } else {
@@ -150,14 +172,14 @@ k_nelder_mead(const SegDev* __restrict__ segs, int nseg, const int32_t* __restri
       double xc[NP];  // inside contraction
       for (int d = 0; d < NP; ++d) xc[d] = cen[d] + 0.5 * (v[NV - 1][d] - cen[d]);
       const double gc = g_at(xc);
-      if (gc < g[NV - 1]) {
+      if (uniform_if(gc < g[NV - 1])) {
         for (int d = 0; d < NP; ++d) v[NV - 1][d] = xc[d];
         g[NV - 1] = gc;
       } else {
         shrink = true;
       }
     }
-    if (shrink) {
+    if (uniform_if(shrink)) {
       for (int i = 1; i < NV; ++i) {
         for (int d = 0; d < NP; ++d) v[i][d] = v[0][d] + 0.5 * (v[i][d] - v[0][d]);
         g[i] = g_at(v[i]);

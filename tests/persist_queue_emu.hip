@@ -50,8 +50,18 @@ int main(int argc, char** argv) {
     return true;
   };
   std::atomic<int64_t> bad{0};
+  // as in the kernel, a tile's completion is counted just before the worker
+  // claims its next tile (or when it leaves the loop)
   auto worker = [&]() {
+    std::atomic<uint32_t>* pend_rel = nullptr;
+    std::atomic<uint32_t>* pend_add = nullptr;
+    auto flush = [&]() {
+      if (pend_rel) (*pend_rel)++;
+      if (pend_add) (*pend_add)++;
+      pend_rel = pend_add = nullptr;
+    };
     for (;;) {
+      flush();
       const int64_t item = (int64_t)head.fetch_add(1);
       if (item >= nitems) break;
       const PUnit u = ps.units[item / PUNIT];
@@ -64,7 +74,7 @@ int main(int argc, char** argv) {
                             : wait(bc(b, 0), 1);
         if (!ok) break;
         done[item]++;
-        bc(b, tile == 0 ? 0 : (tile <= bt.nprep ? 1 : 2))++;
+        pend_rel = &bc(b, tile == 0 ? 0 : (tile <= bt.nprep ? 1 : 2));
         continue;
       }
       const int n = u.id, b = ps.node_batch[n];
@@ -75,17 +85,18 @@ int main(int argc, char** argv) {
         if (!ok) break;
         if (tile >= R(n)) bad++;
         done[item]++;
-        ncn(n, 0)++;
+        pend_rel = &ncn(n, 0);
         continue;
       }
       bool ok = wait(ncn(n, 0), R(n));
       if (ok) ok = wait(bc(b, 2), 1);
       if (!ok) break;
       done[item]++;
-      ncn(n, 1)++;
-      ncn(n, 2)++;
-      bc(b, 3)++;
+      ncn(n, 1)++;  // max mode: the arrival count, taken inside the tile
+      pend_rel = &ncn(n, 2);
+      pend_add = &bc(b, 3);
     }
+    flush();
   };
   std::vector<std::thread> th;
   for (int w = 0; w < W; ++w) th.emplace_back(worker);

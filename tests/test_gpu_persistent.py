@@ -15,12 +15,7 @@ from paper_1003_0844_amd import fstat, synth
 from tests.common import DET, EPH, one_signal, small_segment
 from tests.gpu_common import PREC_TOL, banner, f_error, oracle_map
 
-# The persistent kernel's first GPU run (this file, first test) did not finish:
-# no output for 180 s, killed by the harness, cause not found.  The library
-# runs every call as passes until the cause is shown (kPersistentEnabled in
-# api.hip); these tests stay skipped with it.
-pytestmark = [pytest.mark.gpu,
-              pytest.mark.skip(reason="persistent kernel switched off: its first GPU run did not finish, cause unknown")]
+pytestmark = pytest.mark.gpu
 
 K_HI = 1 << 17   # bins common to all three segments
 

@@ -2,8 +2,7 @@
 (csrc/persist_sched.h) of a three-segment call is checked to be in dependency
 order, and a threaded emulation of the kernel's claim / wait / signal logic
 runs every tile exactly once, for several workgroup counts and spill-slot
-counts (no GPU; the kernel itself is switched off in the library).  The
-emulation is built with the host sanitizers (AddressSanitizer,
+counts (no GPU).  The emulation is built with the host sanitizers (AddressSanitizer,
 UndefinedBehaviorSanitizer) over the schedule code."""
 import os
 import subprocess

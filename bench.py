@@ -96,14 +96,23 @@ def counters_run(args):
           flush=True)
 
 
-def kernel_digest() -> str:
-    """First 16 hex digits of the SHA-256 of the pass-kernel sources."""
+def source_digest(names) -> str:
+    """First 16 hex digits of the SHA-256 of the named kernel sources and of
+    the library's device compile flags (include paths left out), so that a
+    change of either retires the counter records taken before it."""
     import hashlib
+    from paper_1003_0844_amd import _build
     h = hashlib.sha256()
-    for name in KERNEL_SOURCES:
+    for name in names:
         with open(os.path.join(ROOT, "paper_1003_0844_amd", "csrc", name), "rb") as f:
             h.update(name.encode() + b"\0" + f.read())
+    h.update(" ".join(f for f in _build.common_flags() if not f.startswith("-I")).encode())
     return h.hexdigest()[:16]
+
+
+def kernel_digest() -> str:
+    """The digest of the pass-kernel sources (source_digest)."""
+    return source_digest(KERNEL_SOURCES)
 
 
 def traffic_record(kernel: str, sched: dict, nfft: int, interbin: bool):
@@ -135,12 +144,7 @@ def flop_record(kernels: str, n: int):
     from the committed counter summaries (profiles/*flops*.md, lines
     'record: kernels=... n=... digest=... flop_per_candidate=...'), or None
     when none matches the current sources of those kernels."""
-    import hashlib
-    h = hashlib.sha256()
-    for name in GRAD_SOURCES:
-        with open(os.path.join(ROOT, "paper_1003_0844_amd", "csrc", name), "rb") as f:
-            h.update(name.encode() + b"\0" + f.read())
-    digest = h.hexdigest()[:16]
+    digest = source_digest(GRAD_SOURCES)
     if not os.path.isdir(PROFILES):
         return None
     for name in sorted(os.listdir(PROFILES)):
@@ -317,6 +321,7 @@ def uneven_leg():
     graph = plan.graph_max(nodes, 0, k_hi)
     graph.launch()
     s = _median_time(graph.launch, 3)
+    ref = (graph.outputs["Fmax"].clone(), graph.outputs["kmax"].clone())
     graph.close()
     scheds = {}
     for i, (d, _, _, _) in enumerate(segs):
@@ -325,11 +330,26 @@ def uneven_leg():
     torch.cuda.empty_cache()
     gbs = nbytes / s / 1e9
     log("uneven: %.0f nodes/s (%.3f s per launch), %.1f GB/s algorithmic" % (len(nodes) / s, s, gbs))
+    # the same call as one launch of the persistent kernel, recorded in a graph
+    pp = fstat.Plan(specs, fstat.default_detector(), fstat.Ephemeris(), interp=fstat.LINEAR_UP2, prec=fstat.FP32,
+                    launch=fstat.LAUNCH_PERSISTENT)
+    gp = pp.graph_max(nodes, 0, k_hi)
+    gp.launch()
+    sp = _median_time(gp.launch, 2)
+    same = bool(torch.equal(gp.outputs["Fmax"], ref[0]) and torch.equal(gp.outputs["kmax"], ref[1]))
+    gp.close()
+    pp.status()
+    del pp
+    torch.cuda.empty_cache()
+    log("uneven, persistent launch: %.0f nodes/s (%.3f s per launch), outputs equal: %s" % (len(nodes) / sp, sp, same))
     return {"workload": u.name + ", per-node maximum on bins [0, %d), LINEAR_UP2, FP32 with FP64 phase" % k_hi,
-            "launch": "one HIP-graph launch of the whole call (median of 3)",
+            "launch": "one HIP-graph launch of the whole call as passes (median of 3)",
             "nodes": int(len(nodes)), "value": round(len(nodes) / s, 1), "unit": "nodes/s", "s_per_call": round(s, 4),
             "bytes_per_node": round(nbytes / len(nodes)), "path_GBps": round(gbs, 1),
-            "path_frac": round(gbs / HBM_PEAK_GBS, 4), "schedule_by_days": scheds}
+            "path_frac": round(gbs / HBM_PEAK_GBS, 4), "schedule_by_days": scheds,
+            "persistent": {"launch": "one HIP-graph launch of one persistent kernel over the whole call (median of 2)",
+                           "value": round(len(nodes) / sp, 1), "unit": "nodes/s", "s_per_call": round(sp, 4),
+                           "outputs_equal_to_passes": same}}
 
 
 def large6d_leg():

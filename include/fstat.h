@@ -141,7 +141,10 @@ typedef struct {
                                       (the same tile code runs in both). */
 /* Environment: FSTAT_STREAMS=1 (or 2) at plan creation fixes the stream mode
  * of every segment (see fstat_plan_schedule) instead of the default or tuned
- * one; meant for per-kernel timing. */
+ * one; meant for per-kernel timing.  FSTAT_PERSIST_SLOTS (3..128, default
+ * 128: spill slots of nfft x 16 bytes each) and FSTAT_PERSIST_CHUNK (a
+ * divisor of 64, default 32: tiles a workgroup claims at once) set the
+ * pipeline of FSTAT_LAUNCH_PERSISTENT; the outputs do not depend on them. */
 
 typedef struct fstat_plan_s *fstat_plan_t;
 

@@ -77,7 +77,8 @@ struct fstat_plan_s {
   int launch = 0;                // FSTAT_LAUNCH_PASSES / FSTAT_LAUNCH_PERSISTENT
   uint32_t* d_error = nullptr;   // sticky error flag of persistent launches
   int persist_blocks[3] = {0, 0, 0};  // resident workgroups of the persistent kernel per output mode
-  int persist_slots = 8;         // spill slots of a persistent launch (FSTAT_PERSIST_SLOTS)
+  int persist_slots = 128;       // spill slots of a persistent launch (FSTAT_PERSIST_SLOTS)
+  int persist_chunk = 32;        // tiles a workgroup of the persistent kernel claims at once (FSTAT_PERSIST_CHUNK)
   uint64_t spin_ticks = 0;       // wall-clock ticks a wait of the persistent kernel may last
 };
 
@@ -639,9 +640,10 @@ fstat_status launch_persistent(fstat_plan_s* p, const PersistSched& ps, void* ws
     a.coef[k] = cv.take<SkyCoef>(ps.max_sky);
   }
   a.spill = cv.take<Pair<float>>((size_t)ps.nslots * ps.slot_elems);
-  a.part = cv.take<MaxPartial>((size_t)ps.nslots * 1024);
-  a.cnt = cv.take<uint32_t>(ps.ncnt);
+  a.cnt = cv.take<uint32_t>(ps.nzero);
+  a.best = reinterpret_cast<unsigned long long*>(a.cnt + ps.best_off);
   a.head = cv.take<unsigned long long>(1);
+  a.chunk = p->persist_chunk;
   a.segs = p->d_segs;
   a.nitems = (int64_t)ps.units.size() * PUNIT;
   a.nbatch = (int32_t)ps.batches.size();
@@ -661,7 +663,7 @@ fstat_status launch_persistent(fstat_plan_s* p, const PersistSched& ps, void* ws
   go.xing = out->crossings;
   go.n_xing = out->n_crossings;
   go.max_xing = out->max_crossings;
-  HIP_TRY(fsk::persist_zero(a.cnt, ps.ncnt, a.head, st));
+  HIP_TRY(fsk::persist_zero(a.cnt, ps.nzero, a.head, st));
   if (out->mode == 2) HIP_TRY(fsk::zero_u64(out->n_crossings, st));
   return from_hip(fsk::grid_persistent(a, mode, p->persist_blocks[mode], st));
 }
@@ -895,7 +897,11 @@ fstat_status fstat_plan(const fstat_segment* segs, int32_t nseg, const fstat_det
   p->launch = opt->launch;
   if (const char* sl = std::getenv("FSTAT_PERSIST_SLOTS")) {
     const int v = std::atoi(sl);
-    if (v >= 3 && v <= 64) p->persist_slots = v;
+    if (v >= 3 && v <= 128) p->persist_slots = v;
+  }
+  if (const char* ch = std::getenv("FSTAT_PERSIST_CHUNK")) {
+    const int v = std::atoi(ch);
+    if (v >= 1 && v <= PUNIT && PUNIT % v == 0) p->persist_chunk = v;
   }
   p->segs.resize(nseg);
   for (int i = 0; i < nseg; ++i) {

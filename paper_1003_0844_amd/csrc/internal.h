@@ -118,10 +118,11 @@ struct PersistArgs {
   SkyCoef* coef[2];
   void* spill;                // nslots x slot_elems spill elements; node n uses slot n % nslots
   int64_t slot_elems;
-  MaxPartial* part;           // nslots x 1024 max partials
+  unsigned long long* best;   // max mode, per node: the largest F so far as an ordered key (max_key)
   GridOut out;
   unsigned long long* head;   // tiles claimed
-  uint32_t* cnt;              // completion counters: 4 per batch, then 3 per node
+  int32_t chunk;              // tiles a workgroup claims at once (a divisor of PUNIT)
+  uint32_t* cnt;              // completion counters: 4 per batch, then 2 per node
   uint32_t* error;            // sticky flag: a wait outlived spin_ticks
   uint64_t spin_ticks;        // wall-clock ticks a wait may last
 };
@@ -156,7 +157,8 @@ hipError_t max_finalize(const MaxPartial* d_part, int nparts, const NodeDev* d_n
 hipError_t zero_u64(unsigned long long* p, hipStream_t st);
 // persist.hip: the whole grid call in one launch (FP32, C = 4096, 64 <= R <=
 // 1024, no interbinning); counters, head and spill must be zeroed / sized by
-// the caller (persist_zero clears counters and head)
+// the caller (persist_zero clears the n32 words of counters and per-node
+// maximum keys at cnt, and head)
 int persistent_blocks(int mode);
 hipError_t persist_zero(uint32_t* cnt, int64_t n32, unsigned long long* head, hipStream_t st);
 hipError_t grid_persistent(const PersistArgs& a, int mode, int blocks, hipStream_t st);

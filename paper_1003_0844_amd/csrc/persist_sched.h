@@ -31,6 +31,8 @@ struct PersistSched {
   int64_t slot_elems = 0;
   int nslots = 0;
   int64_t ncnt = 0;       // 32-bit counters
+  int64_t best_off = 0;   // 32-bit words from the counters to the per-node maximum keys (max mode)
+  int64_t nzero = 0;      // 32-bit words the launch clears: counters and keys
   size_t desc_bytes = 0, need_ws = 0;
   bool ordered = false;   // every tile's dependencies lie earlier in the queue (checked)
 };
@@ -66,7 +68,7 @@ inline bool queue_is_ordered(const PersistSched& ps) {
 // Nodes ordered by FFT length (longest first), then segment and sky position;
 // batches of up to 64 sky positions of one segment; then the queue: the sky
 // stage of batches 0 and 1, and for every node its pass-1 tiles followed by
-// the pass-2 tiles of the node L = nslots - 2 places earlier.  The sky stage of
+// the pass-2 tiles of the node L = nslots / 2 places earlier.  The sky stage of
 // batch c + 1 (whose sky set batch c - 1 used) goes in after node L + 1 of
 // batch c, once every pass-2 tile of batch c - 1 is in the queue.  Every
 // tile's dependencies thus lie earlier in the queue.
@@ -108,7 +110,10 @@ inline void schedule_persistent(const std::vector<SegShape>& segs, int nslots, c
   }
   const int nb = (int)ps.batches.size();
   ps.nslots = nslots;
-  const int L = ps.nslots - 2;
+  // Pass 2 of a node L nodes after its pass 1, and pass 1 of a node nslots - L
+  // nodes after pass 2 of the slot's previous user: both gaps as wide as the
+  // slots allow, since a workgroup claims several tiles ahead.
+  const int L = ps.nslots / 2;
   for (const auto& b : ps.batches) {
     const SegShape& d = segs[b.seg];
     ps.max_quads = std::max(ps.max_quads, (size_t)b.nsky * d.R * d.Ceff * sizeof(Quad<float>));
@@ -149,14 +154,16 @@ inline void schedule_persistent(const std::vector<SegShape>& segs, int nslots, c
   ps.ordered = queue_is_ordered(ps);
   ps.tw.resize(segs.size());
   for (size_t s = 0; s < segs.size(); ++s) ps.tw[s] = segs[s].tw;
-  ps.ncnt = 4 * (int64_t)nb + 3 * (int64_t)ps.ndev.size();
+  ps.ncnt = 4 * (int64_t)nb + 2 * (int64_t)ps.ndev.size();
+  ps.best_off = (ps.ncnt + 1) / 2 * 2;
+  ps.nzero = ps.best_off + 2 * (int64_t)ps.ndev.size();
   ps.desc_bytes = psched_align(ps.sky_ad.size() * sizeof(double)) + psched_align(ps.ndev.size() * sizeof(NodeDev)) +
                   psched_align(ps.node_batch.size() * sizeof(int32_t)) + psched_align(ps.batches.size() * sizeof(PBatch)) +
                   psched_align(ps.units.size() * sizeof(PUnit)) + psched_align(ps.tw.size() * sizeof(PSegTw));
   ps.need_ws = ps.desc_bytes + 2 * (psched_align(ps.max_quads) + psched_align(ps.max_sky * sizeof(SkyConst)) +
                                     psched_align(ps.max_sky * sizeof(SkyCoef))) +
                psched_align((size_t)ps.nslots * ps.slot_elems * sizeof(Pair<float>)) +
-               psched_align((size_t)ps.nslots * 1024 * sizeof(MaxPartial)) + psched_align(ps.ncnt * sizeof(uint32_t)) +
+               psched_align(ps.nzero * sizeof(uint32_t)) +
                psched_align(sizeof(unsigned long long)) + 4096;
 }
 

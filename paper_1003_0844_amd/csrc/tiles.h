@@ -95,9 +95,12 @@ __device__ __forceinline__ void pass1_tile(const SegDev& sg, const Quad<T>* __re
 }
 
 // Pass 2 for the column block cb (B2 adjacent k2) of one node: src is the
-// node's spill, part its C/B2 max partials (mode 1), lds lds_slots(R, B2) slots.
+// node's spill, lds lds_slots(R, B2) slots.  Mode 1: the block's largest F
+// and its bin (ties to the lowest bin; k = INT64_MAX if no bin of the block
+// lies in [k_lo, k_hi)) are returned in thread 0, and stored at part[cb]
+// unless part is null.
 template <typename T, int R, int MODE>
-__device__ __forceinline__ void pass2_tile(const SegDev& sg, const Pair<T>* __restrict__ spill_node,
+__device__ __forceinline__ MaxPartial pass2_tile(const SegDev& sg, const Pair<T>* __restrict__ spill_node,
                                            const NodeDev& node, const SkyCoef& cf, const cpx<T>* __restrict__ twR,
                                            const GridOut& out, int cb, MaxPartial* __restrict__ part,
                                            lds_t<Pair<T>>* __restrict__ lds) {
@@ -171,9 +174,10 @@ __device__ __forceinline__ void pass2_tile(const SegDev& sg, const Pair<T>* __re
           best = sf[w];
           bestk = sk[w];
         }
-      part[cb] = MaxPartial{best, bestk};
+      if (part) part[cb] = MaxPartial{best, bestk};
     }
   }
+  return MaxPartial{best, bestk};
 }
 
 template <typename T> struct DataPtrs;

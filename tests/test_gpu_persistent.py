@@ -5,7 +5,8 @@ code runs in both), and the oracle within the FP32 bar.
 
 Segments of 2^18, 2^19 and 2^20 bins (R = 64, 128, 256 at C = 4096: both
 spill layouts), gaps in one, four sky batches (the two sky sets are reused),
-spill slots down to the minimum, all three output modes, and graph replays."""
+spill slots down to the minimum, claims of 1 to 64 tiles, all three output
+modes, and graph replays."""
 import numpy as np
 import pytest
 import torch
@@ -74,12 +75,14 @@ def case():
     return segs, sig, nodes, out
 
 
-@pytest.mark.parametrize("slots", [None, "3"])
-def test_persistent_equals_passes(case, slots, monkeypatch):
+@pytest.mark.parametrize("slots,chunk", [(None, None), ("3", "1"), ("3", "64"), ("6", "8")])
+def test_persistent_equals_passes(case, slots, chunk, monkeypatch):
     segs, sig, nodes, ref = case
     if slots:
         monkeypatch.setenv("FSTAT_PERSIST_SLOTS", slots)
-    banner("persistent", "slots", slots)
+    if chunk:
+        monkeypatch.setenv("FSTAT_PERSIST_CHUNK", chunk)
+    banner("persistent", "slots", slots, "chunk", chunk)
     plan = _plan(segs, fstat.LAUNCH_PERSISTENT)
     got = _outputs(plan, nodes, 9.0)
     plan.status()

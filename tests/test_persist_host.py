@@ -1,8 +1,8 @@
 """The persistent launch's work queue on the CPU: the library's schedule
 (csrc/persist_sched.h) of a three-segment call is checked to be in dependency
 order, and a threaded emulation of the kernel's claim / wait / signal logic
-runs every tile exactly once, for several workgroup counts and spill-slot
-counts (no GPU).  The emulation is built with the host sanitizers (AddressSanitizer,
+runs every tile exactly once, for several workgroup counts, spill-slot
+counts and claim sizes (no GPU).  The emulation is built with the host sanitizers (AddressSanitizer,
 UndefinedBehaviorSanitizer) over the schedule code."""
 import os
 import subprocess
@@ -26,9 +26,10 @@ def emu(tmp_path_factory):
     return exe
 
 
-@pytest.mark.parametrize("threads,slots", [(16, 3), (64, 8), (768, 8), (256, 5)])
-def test_queue_runs_every_tile_once(emu, threads, slots):
-    r = subprocess.run([emu, str(threads), str(slots)], capture_output=True, text=True, timeout=120)
+@pytest.mark.parametrize("threads,slots,chunk", [(16, 3, 1), (64, 8, 1), (768, 8, 1), (256, 5, 4), (100, 3, 16),
+                                                 (768, 32, 16), (768, 8, 64), (33, 4, 8)])
+def test_queue_runs_every_tile_once(emu, threads, slots, chunk):
+    r = subprocess.run([emu, str(threads), str(slots), str(chunk)], capture_output=True, text=True, timeout=120)
     assert r.returncode == 0, r.stdout + r.stderr
     assert "ordered 1" in r.stdout
     assert "error 0, items never run 0, run twice 0, bad tiles 0" in r.stdout, r.stdout

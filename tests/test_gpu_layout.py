@@ -78,3 +78,34 @@ def test_spill_layouts_against_oracle(prec, C, interbin, tmp_path, monkeypatch):
     assert int(cnt.cpu().item()) == len(want) == len(got)
     assert sorted(zip(got["node"].tolist(), got["k"].tolist())) == sorted(map(tuple, want.tolist()))
     assert np.array_equal(np.sort(got["F"]), np.sort(F64[F64 > thr]))
+
+
+
+def test_sub_bands_and_unaligned_maps_equal_the_full_map(tmp_path, monkeypatch):
+    # FP32 with R = 256 (B2 = 16, the 2-day map's pass 2): a band [k_lo, k_hi)
+    # is the same columns of the full map, whatever the band's alignment to the
+    # column blocks, and a map that starts 4 bytes off 16-byte alignment gets
+    # the same values, bit for bit
+    import torch
+    w = synth.TINY
+    g, x, sigs = synth.segment_data(w)
+    cache = tmp_path / "tune.txt"
+    cache.write_text("fstat-tune-v3 %d %d %d %d %d 2 1\n" % (fstat.FP32, w.interp, w.nfft, w.n, 256))
+    monkeypatch.setenv("FSTAT_TUNE_CACHE", str(cache))
+    banner("map sub-bands", "nfft", w.nfft)
+    plan = fstat.Plan([fstat.SegmentSpec(x=x, dt=w.dt, n_days=w.days, nfft=w.nfft)], fstat.detector_spec(DET),
+                      fstat.ephemeris_spec(EPH), interp=w.interp, prec=fstat.FP32, autotune=True)
+    assert plan.schedule()["R"] == 256 and plan.schedule()["B2"] == 16
+    al, de = synth.sky_uniform(synth.rng(11), 3)
+    nodes = fstat.nodes_array(al, de, [0.0, -4e-10, -9e-10])
+    half = w.nfft // 2
+    full = plan.grid_map(nodes, 0, half).clone()
+    for lo, hi in [(0, half - 1), (64, half - 96), (63, half - 96), (17, 4113)]:
+        part = plan.grid_map(nodes, lo, hi).clone()
+        torch.cuda.synchronize()
+        assert torch.equal(part, full[:, lo:hi]), (lo, hi)
+    buf = torch.full((len(nodes) * half + 1,), float("nan"), dtype=torch.float32, device="cuda")
+    skew = buf[1:].view(len(nodes), half)
+    plan.grid_map(nodes, 0, half, skew)
+    torch.cuda.synchronize()
+    assert torch.equal(skew, full)

@@ -351,7 +351,10 @@ class Lattice:
 
 
 class Plan:
-    """A plan of fstat_plan: segments on the device, prepared for grid calls."""
+    """A plan of fstat_plan: segments on the device, prepared for grid calls.
+    launch: LAUNCH_PASSES (a sequence of pass launches per batch, the default)
+    or LAUNCH_PERSISTENT (one persistent kernel per call where it applies;
+    the same outputs, bit for bit)."""
 
     def __init__(self, segments: Sequence[SegmentSpec], det: Detector, eph: Ephemeris,
                  interp: int = LINEAR_UP2, prec: int = FP32, device: int = 0, max_batch: int = 0,

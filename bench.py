@@ -55,6 +55,10 @@ def parse():
                     help="short run for hardware-counter collection: one grid call on two node batches "
                          "of the benchmark's (autotuned) schedule "
                          "and a 1 GiB device copy of known size (the calibration of the byte counters)")
+    ap.add_argument("--log", default=None, metavar="FILE",
+                    help="append to FILE one JSON line per node chunk of every timed step (the chunk's node "
+                         "range, the place a resumed run restarts from, its HIP-event time and nodes/s), then "
+                         "the result line")
     ap.add_argument("--refine-counters", action="store_true",
                     help="short run for FP64 instruction counters: one F + gradient call (fstat_grad) on the "
                          "4096 refinement candidates")
@@ -478,22 +482,38 @@ def main():
         % (sched, time.perf_counter() - t_plan))
     F = torch.empty((chunk, width), dtype=torch.float32, device="cuda")
 
-    def step():
+    def step(marks=None):
         for c0 in range(0, nn, chunk):
             part = nodes[c0:c0 + chunk]
             plan.grid_map(part, 0, half, F[:len(part)], interbin=ib)
+            if marks is not None:   # --log: an event after each node chunk
+                ev = torch.cuda.Event(enable_timing=True)
+                ev.record()
+                marks.append((c0, c0 + len(part), ev))
 
     for i in range(args.warmup):
         step()
         torch.cuda.synchronize()
         log("warmup step %d done" % i)
     plan.profile(True)
+    # with --log, an event after every node chunk of every step (no
+    # synchronisation inside the timed region)
+    marks = [] if args.log else None
+    start = torch.cuda.Event(enable_timing=True) if args.log else None
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    if start is not None:
+        start.record()
     for i in range(args.steps):
-        step()
+        step(marks)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    chunk_log = []
+    if marks is not None:
+        prev = start
+        for j, (c0, c1, ev) in enumerate(marks):
+            chunk_log.append({"step": j // -(-nn // chunk), "nodes": [c0, c1], "ms": round(prev.elapsed_time(ev), 3)})
+            prev = ev
     if nn > chunk:   # leave the first chunk's map in F for the FP64 comparison
         plan.grid_map(nodes[:chunk], 0, half, F, interbin=ib)
         torch.cuda.synchronize()
@@ -574,6 +594,13 @@ def main():
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(w, x, nodes, args.cpu_seconds, nfft, ib)
+    if args.log:
+        with open(args.log, "a") as f:
+            for rec in chunk_log:
+                n_c = rec["nodes"][1] - rec["nodes"][0]
+                f.write(json.dumps(dict(rec, nodes_per_s=round(n_c / (rec["ms"] * 1e-3), 1),
+                                        workload=out["config"]["workload"])) + "\n")
+            f.write(json.dumps(out) + "\n")
     print(json.dumps(out), flush=True)
 
 

@@ -78,12 +78,14 @@ def build_library(verbose: bool = False, sanitize: bool = False, out: str = "") 
     with ThreadPoolExecutor(max_workers=min(len(SOURCES), 8)) as ex:
         objs = list(ex.map(compile_one, SOURCES))
     tmp = lib + ".tmp%d" % os.getpid()
+    rocm_lib = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "lib")
+    # roctx: the ranges the library marks around its calls
+    libs = ["-L" + rocm_lib, "-lrocprofiler-sdk-roctx", "-Wl,-rpath," + rocm_lib]
     if sanitize:
-        rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
         cmd = [_clangxx(), "-shared", "-fPIC", "-shared-libasan", "-fsanitize=address,undefined", *objs,
-               "-L" + os.path.join(rocm, "lib"), "-lamdhip64", "-Wl,-rpath," + os.path.join(rocm, "lib"), "-o", tmp]
+               "-lamdhip64", *libs, "-o", tmp]
     else:
-        cmd = [hipcc, "--offload-arch=" + ARCH, "-shared", "-fPIC", *objs, "-o", tmp]
+        cmd = [hipcc, "--offload-arch=" + ARCH, "-shared", "-fPIC", *objs, *libs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed:\n" + r.stderr[-4000:])

@@ -9,9 +9,22 @@
 #include <new>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "../../include/fstat.h"
 #include "internal.h"
 #include "persist_sched.h"
+
+namespace {
+// A roctx range over one call of the library (rocprofv3 --marker-trace shows
+// it beside the kernels; without a tracer attached it costs a function call).
+struct Range {
+  explicit Range(const char* what) { roctxRangePushA(what); }
+  ~Range() { roctxRangePop(); }
+  Range(const Range&) = delete;
+  Range& operator=(const Range&) = delete;
+};
+}  // namespace
 
 namespace {
 
@@ -870,6 +883,7 @@ const char* fstat_strerror(fstat_status s) {
 
 fstat_status fstat_plan(const fstat_segment* segs, int32_t nseg, const fstat_detector* det,
                         const fstat_ephemeris* eph, const fstat_options* opt, fstat_plan_t* out) {
+  Range rg("fstat_plan");
   if (!segs || nseg <= 0 || !det || !eph || !opt || !out) return FSTAT_EINVAL;
   if (opt->interp < 0 || opt->interp > 2 || opt->prec < 0 || opt->prec > 1 || opt->max_batch < 0 ||
       opt->max_batch > 256 || opt->autotune < 0 || opt->autotune > 1 ||
@@ -1055,6 +1069,7 @@ extern "C" {
 
 fstat_status fstat_grid(fstat_plan_t p, const fstat_node* nodes, int64_t n_nodes, const fstat_out* out,
                         void* hip_stream) {
+  Range rg("fstat_grid");
   fstat_status rc = check_grid_args(p, nodes, n_nodes, out);
   if (rc != FSTAT_OK) return rc;
   DeviceGuard guard(p->device);
@@ -1065,6 +1080,7 @@ fstat_status fstat_grid(fstat_plan_t p, const fstat_node* nodes, int64_t n_nodes
 
 fstat_status fstat_graph_create(fstat_plan_t p, const fstat_node* nodes, int64_t n_nodes, const fstat_out* out,
                                 fstat_graph_t* g_out) {
+  Range rg("fstat_graph_create");
   if (!g_out) return FSTAT_EINVAL;
   fstat_status rc = check_grid_args(p, nodes, n_nodes, out);
   if (rc != FSTAT_OK) return rc;
@@ -1110,6 +1126,7 @@ fstat_status fstat_graph_create(fstat_plan_t p, const fstat_node* nodes, int64_t
 }
 
 fstat_status fstat_graph_launch(fstat_graph_t g, void* hip_stream) {
+  Range rg("fstat_graph_launch");
   if (!g || !g->exec) return FSTAT_EINVAL;
   DeviceGuard guard(g->plan->device);
   if (!guard.ok) return FSTAT_EDEVICE;
@@ -1231,6 +1248,7 @@ fstat_status fstat_amplitudes(fstat_plan_t p, const double* params, const int32_
 
 fstat_status fstat_grad(fstat_plan_t p, const double* params, const int32_t* seg, int64_t n, double* F, double* dF,
                         void* hip_stream) {
+  Range rg("fstat_grad");
   if (!p || !params || n <= 0 || !F) return FSTAT_EINVAL;
   if (n > (int64_t)INT32_MAX) return FSTAT_EUNSUPPORTED;
   DeviceGuard guard(p->device);

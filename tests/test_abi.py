@@ -29,6 +29,15 @@ def test_library_exports_every_declared_symbol():
     assert set(names) == set(fstat.EXPORTS)
 
 
+def test_library_marks_its_calls_with_roctx_ranges():
+    # the plan / grid / graph / gradient entry points push and pop a roctx range
+    # (rocprofv3 --marker-trace); the library links the roctx library for it
+    import subprocess
+    out = subprocess.run(["nm", "-D", fstat.LIB_PATH], capture_output=True, text=True, check=True).stdout
+    undefined = {line.split()[-1] for line in out.splitlines() if " U " in line}
+    assert {"roctxRangePushA", "roctxRangePop"} <= undefined
+
+
 def test_strerror():
     L = fstat.lib()
     assert L.fstat_strerror(0) == b"ok"

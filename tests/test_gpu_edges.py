@@ -83,6 +83,36 @@ def test_single_bin_ranges():
     assert torch.equal(Fmax, full[:, half - 1]) and bool((kmax == half - 1).all())
 
 
+def test_node_ranges_resume_bit_for_bit():
+    # a grid call is a pure function of (plan, nodes): re-issuing it from any
+    # node index (a resumed search) gives the same rows, maxima and crossings
+    seg = small_segment(days=1, dt=13.0, seed=57, nfft=16384)
+    banner("node-range resume")
+    plan = make_plan([seg], method.LINEAR_UP2, fstat.FP32, max_batch=4)
+    g = synth.rng(58)
+    al, de = synth.sky_uniform(g, 5)
+    nodes = fstat.nodes_array(np.repeat(al, 3), np.repeat(de, 3), np.tile([0.0, -3e-10, -7e-10], 5))
+    half = seg.fft_len // 2
+    full = plan.grid_map(nodes, 0, half).clone()
+    Fm, km = [t.clone() for t in plan.grid_max(nodes, 0, half)]
+    thr = float(torch.quantile(full.double().flatten()[::7], 0.99))
+    rec, cnt = plan.grid_crossings(nodes, 0, half, thr, 1 << 16)
+    want = sorted(zip(*[fstat.Plan.read_crossings(rec, cnt)[c].tolist() for c in ("node", "k", "F")]))
+    for cut in (1, 7, 14):
+        a = fstat.nodes_array(nodes["alpha"][:cut], nodes["delta"][:cut], nodes["fdot"][:cut])
+        b = fstat.nodes_array(nodes["alpha"][cut:], nodes["delta"][cut:], nodes["fdot"][cut:])
+        assert torch.equal(torch.cat([plan.grid_map(a, 0, half), plan.grid_map(b, 0, half)]), full), cut
+        ma, ka = plan.grid_max(a, 0, half)
+        mb, kb = plan.grid_max(b, 0, half)
+        assert torch.equal(torch.cat([ma, mb]), Fm) and torch.equal(torch.cat([ka, kb]), km), cut
+        got = []
+        for part, off in ((a, 0), (b, cut)):
+            r, c = plan.grid_crossings(part, 0, half, thr, 1 << 16)
+            x = fstat.Plan.read_crossings(r, c)
+            got += [(n + off, k, F) for n, k, F in zip(x["node"].tolist(), x["k"].tolist(), x["F"].tolist())]
+        assert sorted(got) == want, cut
+
+
 def test_argument_checks_with_a_plan():
     seg = small_segment(days=1, dt=13.0, seed=55, nfft=16384)
     banner("argument checks")

@@ -445,7 +445,10 @@ fstat_status fstat_bin_params(fstat_plan_t p, const fstat_node *nodes, const int
 /* Waits for the plan's device, then reports and clears the plan's error flag:
  * FSTAT_EDEVICE if a persistent launch (FSTAT_LAUNCH_PERSISTENT) stopped early
  * since the last call (a wait inside the kernel outlived its bound; the
- * outputs of that call are incomplete), FSTAT_OK otherwise. */
+ * outputs of that call are incomplete), FSTAT_OK otherwise.  The flag stays
+ * set until this call clears it: persistent launches of the plan made in
+ * between stop at once, with incomplete outputs, and are reported by the same
+ * FSTAT_EDEVICE. */
 fstat_status fstat_plan_status(fstat_plan_t p);
 
 /* Plan facts.  Host outputs; any pointer may be NULL. */

@@ -144,7 +144,10 @@ typedef struct {
  * one; meant for per-kernel timing.  FSTAT_PERSIST_SLOTS (3..128, default
  * 128: spill slots of nfft x 16 bytes each) and FSTAT_PERSIST_CHUNK (a
  * divisor of 64, default 32: tiles a workgroup claims at once) set the
- * pipeline of FSTAT_LAUNCH_PERSISTENT; the outputs do not depend on them. */
+ * pipeline of FSTAT_LAUNCH_PERSISTENT; the outputs do not depend on them.
+ * FSTAT_PERSIST_SPIN_TICKS lowers the bound of the persistent kernel's waits
+ * (wall-clock ticks, default 2 s worth; 0: a wait not satisfied at once
+ * expires): a way to exercise the error path of fstat_plan_status. */
 
 typedef struct fstat_plan_s *fstat_plan_t;
 

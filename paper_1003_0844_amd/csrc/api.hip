@@ -948,6 +948,12 @@ fstat_status fstat_plan(const fstat_segment* segs, int32_t nseg, const fstat_det
     int khz = 0;
     e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, opt->device);
     p->spin_ticks = (uint64_t)(khz > 0 ? khz : 100000) * 2000ull;  // 2 s
+    // a shorter bound (0: a wait not satisfied at once expires), for tests of the error path
+    if (const char* sp = std::getenv("FSTAT_PERSIST_SPIN_TICKS")) {
+      char* end = nullptr;
+      const long long v = std::strtoll(sp, &end, 10);
+      if (end != sp && v >= 0) p->spin_ticks = std::min<uint64_t>(p->spin_ticks, (uint64_t)v);
+    }
   }
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking);
   for (hipEvent_t* ev : {&p->ev_p1[0], &p->ev_p1[1], &p->ev_p2[0], &p->ev_p2[1], &p->ev_sky[0], &p->ev_sky[1], &p->ev_join})

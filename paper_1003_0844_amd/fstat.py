@@ -40,7 +40,6 @@ class FStatError(RuntimeError):
     def __init__(self, status: int, what: str):
         super().__init__("%s: %s (%d)" % (what, lib().fstat_strerror(status).decode(), status))
         self.status = status
-        self.status = status
 
 
 # --------------------------------------------------------------------------

@@ -137,6 +137,26 @@ def test_persistent_graph_replays(case):
     plan.status()
 
 
+def test_an_expired_wait_stops_the_kernel_and_is_reported(case, monkeypatch):
+    # waits bounded to 0 ticks: the first wait not satisfied at once expires,
+    # sets the plan's flag, and every workgroup leaves the queue (the kernel
+    # ends normally); fstat_plan_status reports it once and clears it
+    segs, sig, nodes, ref = case
+    monkeypatch.setenv("FSTAT_PERSIST_SPIN_TICKS", "0")
+    banner("persistent expired wait")
+    plan = _plan(segs, fstat.LAUNCH_PERSISTENT)
+    F = plan.grid_map(nodes, 0, K_HI)
+    with pytest.raises(fstat.FStatError) as e:
+        plan.status()
+    assert e.value.status == fstat.EDEVICE
+    plan.status()  # cleared
+    del F, plan
+    monkeypatch.delenv("FSTAT_PERSIST_SPIN_TICKS")
+    plan = _plan(segs, fstat.LAUNCH_PERSISTENT)
+    assert torch.equal(plan.grid_map(nodes, 0, K_HI), ref[0])
+    plan.status()
+
+
 def test_calls_the_kernel_does_not_hold_run_as_passes():
     # interbinning, and an FFT length below 2^18, fall back to the passes
     seg = small_segment(days=1, dt=13.0, seed=76, nfft=16384)

@@ -205,6 +205,29 @@ def copy_probe_gbps():
     return best, best_blocks
 
 
+def spill_write_probe_gbps(nodes: int, R: int, C: int, b2: int) -> float:
+    """The rate of the first FFT pass's spill stores alone (the library's
+    probe of the same workgroups, thread-to-bin map and layout, without the
+    transform): bytes over the median of 5 timed launches after one untimed."""
+    import torch
+    from paper_1003_0844_amd import fstat
+    buf = torch.empty((nodes * R * C, 4), dtype=torch.float32, device="cuda")
+    fstat.spill_write_probe(buf, nodes, R, C, b2)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(5):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record()
+        fstat.spill_write_probe(buf, nodes, R, C, b2)
+        ev[1].record()
+        torch.cuda.synchronize()
+        ts.append(ev[0].elapsed_time(ev[1]))
+    ts.sort()
+    del buf
+    torch.cuda.empty_cache()
+    return nodes * R * C * 16 / (ts[2] * 1e-3) / 1e9
+
+
 def lattice_workload(w, x, rule):
     """The full-sky lattice of the segment (Sec. IV, C0 = 3/4) over the uniform
     grid's spindown range, f_sky at the top of the band."""
@@ -589,6 +612,13 @@ def main():
     out["roofline"]["path_frac_of_copy"] = round(path_gbs / cp, 4)
     log("copy probe: %.1f GB/s (%d workgroups); path %.1f GB/s = %.1f %% of it" % (cp, cp_blocks, path_gbs,
                                                                                  100 * path_gbs / cp))
+    if out["roofline"]["kernel"] == "k_pass1":
+        b2 = sched["B2"] if sched["B2"] * 16 < 512 else 0   # the spill layout pass 1 writes (blocked or row-major)
+        wp = spill_write_probe_gbps(sched["batch"], sched["R"], sched["C"], b2)
+        out["roofline"]["spill_write_probe_GBps"] = round(wp, 1)
+        out["roofline"]["frac_of_spill_write_probe"] = round(out["roofline"]["achieved"] / wp, 4)
+        log("spill write probe: %.1f GB/s; k_pass1 %.1f GB/s = %.1f %% of it"
+            % (wp, out["roofline"]["achieved"], 100 * out["roofline"]["achieved"] / wp))
     if not args.no_extra and lat is None and not ib:
         out["workloads"] = {"uneven_segments": uneven_leg(), "large6d": large6d_leg(), "refinement": refine_leg()}
     if not args.no_cpu_baseline:

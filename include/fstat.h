@@ -504,6 +504,17 @@ const char *fstat_strerror(fstat_status s);
  * grid path's own.  FSTAT_EINVAL for bad arguments. */
 fstat_status fstat_copy_probe(void *dst, const void *src, int64_t bytes, int32_t blocks, void *hip_stream);
 
+/* Measurement aid: the store pattern of the first FFT pass alone, enqueued on
+ * hip_stream.  For each of `nodes` nodes (dst: nodes x R x C elements of 16
+ * bytes, 16-byte aligned) and each column r < R, one workgroup of C/16
+ * threads writes the C elements of row r, thread t the elements k2 = t +
+ * q C/16 (q < 16), at [k2 / b2][r][k2 % b2] within the node (b2 a power of two
+ * <= C: the blocked spill layout) or [r][k2] (b2 = 0: row-major), with
+ * streaming 16-byte stores of (r, node, 0, 1) as floats.  Timing it gives the
+ * rate the pass's write pattern can reach without its transform.  C in
+ * {1024, 2048, 4096}, 1 <= nodes <= 65535; FSTAT_EINVAL otherwise. */
+fstat_status fstat_spill_write_probe(void *dst, int64_t nodes, int32_t R, int32_t C, int32_t b2, void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -100,7 +100,7 @@ EXPORTS = ("fstat_plan", "fstat_grid", "fstat_graph_create", "fstat_graph_launch
            "fstat_eval", "fstat_eval_exact", "fstat_refine", "fstat_threshold", "fstat_adjoint", "fstat_amplitudes",
            "fstat_grad", "fstat_grad_static", "fstat_plan_info", "fstat_demod_series",
            "fstat_lattice_fisher", "fstat_lattice_build", "fstat_lattice_segment", "fstat_lattice_nodes",
-           "fstat_copy_probe", "fstat_bin_params",
+           "fstat_copy_probe", "fstat_spill_write_probe", "fstat_bin_params",
            "fstat_profile",
            "fstat_profile_read", "fstat_plan_schedule", "fstat_plan_status", "fstat_destroy", "fstat_strerror")
 K_SKY, K_PASS1, K_PASS2, K_OTHER = 0, 1, 2, 3
@@ -139,6 +139,7 @@ def lib():
         L.fstat_bin_params.argtypes = [vp, vp, vp, i64, i32, vp, vp]
         L.fstat_lattice_nodes.argtypes = [P(_Lattice), P(_LatticeRegion), P(_Ephemeris), vp, vp, i64, P(i64)]
         L.fstat_copy_probe.argtypes = [vp, vp, i64, i32, vp]
+        L.fstat_spill_write_probe.argtypes = [vp, i64, i32, i32, i32, vp]
         L.fstat_plan_info.argtypes = [vp, i32, P(i64), P(i64), P(ctypes.c_double), P(i32), P(i32)]
         L.fstat_demod_series.argtypes = [vp, vp, vp, vp]
         L.fstat_profile.argtypes = [vp, i32]
@@ -152,6 +153,7 @@ def lib():
         for name in ("fstat_plan", "fstat_grid", "fstat_graph_create", "fstat_graph_launch", "fstat_amplitudes",
                      "fstat_eval_exact", "fstat_refine", "fstat_threshold", "fstat_lattice_fisher",
                      "fstat_lattice_build", "fstat_lattice_segment", "fstat_lattice_nodes", "fstat_copy_probe",
+                     "fstat_spill_write_probe",
                      "fstat_bin_params",
                      "fstat_eval", "fstat_adjoint", "fstat_grad", "fstat_grad_static", "fstat_plan_info",
                      "fstat_demod_series", "fstat_profile", "fstat_profile_read", "fstat_plan_schedule",
@@ -231,6 +233,15 @@ def copy_probe(dst: torch.Tensor, src: torch.Tensor, blocks: int = 0) -> None:
         raise ValueError("src and dst must be device tensors of the same byte size")
     _check(lib().fstat_copy_probe(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()), nbytes, int(blocks),
                                   _stream_ptr(src.device.index)), "fstat_copy_probe")
+
+
+def spill_write_probe(dst: torch.Tensor, nodes: int, R: int, C: int, b2: int) -> None:
+    """fstat_spill_write_probe on the current stream: the first FFT pass's
+    spill stores alone into dst (nodes x R x C elements of 16 bytes)."""
+    if dst.numel() * dst.element_size() < nodes * R * C * 16:
+        raise ValueError("dst smaller than nodes x R x C x 16 bytes")
+    _check(lib().fstat_spill_write_probe(ctypes.c_void_p(dst.data_ptr()), int(nodes), int(R), int(C), int(b2),
+                                         _stream_ptr(dst.device.index)), "fstat_spill_write_probe")
 
 
 def nodes_array(alpha, delta, fdot, seg=0, bin_offset=0.0) -> np.ndarray:

@@ -131,3 +131,19 @@ def test_copy_probe_rejects_bad_arguments():
     assert L.fstat_copy_probe(vp(4096), vp(4096 + 16), 64, 0, None) == fstat.EINVAL
     assert L.fstat_copy_probe(None, vp(1 << 20), 64, 0, None) == fstat.EINVAL
     assert L.fstat_copy_probe(vp(4096), vp(1 << 20), 64, -1, None) == fstat.EINVAL
+
+
+def test_spill_write_probe_rejects_bad_arguments():
+    # checked before any device work: NULL or misaligned buffer, node count,
+    # first-pass length, block width
+    L = fstat.lib()
+    vp = ctypes.c_void_p
+    assert L.fstat_spill_write_probe(None, 1, 8, 1024, 16, None) == fstat.EINVAL
+    assert L.fstat_spill_write_probe(vp(4100), 1, 8, 1024, 16, None) == fstat.EINVAL
+    assert L.fstat_spill_write_probe(vp(4096), 0, 8, 1024, 16, None) == fstat.EINVAL
+    assert L.fstat_spill_write_probe(vp(4096), 65536, 8, 1024, 16, None) == fstat.EINVAL
+    assert L.fstat_spill_write_probe(vp(4096), 1, 0, 1024, 16, None) == fstat.EINVAL
+    assert L.fstat_spill_write_probe(vp(4096), 1, 8, 512, 16, None) == fstat.EINVAL
+    assert L.fstat_spill_write_probe(vp(4096), 1, 8, 1024, 12, None) == fstat.EINVAL
+    assert L.fstat_spill_write_probe(vp(4096), 1, 8, 1024, 2048, None) == fstat.EINVAL
+    assert L.fstat_spill_write_probe(vp(4096), 1, 8, 1024, -1, None) == fstat.EINVAL

@@ -178,6 +178,29 @@ def test_bin_params_of_two_segments():
         plan.bin_params(bad, k)
 
 
+@pytest.mark.parametrize("C,b2", [(1024, 16), (4096, 8), (2048, 0)])
+def test_spill_write_probe_writes_the_first_pass_layout(C, b2):
+    # every element of nodes x R x C written once, with (r, node) of its
+    # writer at its place in the blocked [k2 / b2][r][k2 % b2] or row-major
+    # [r][k2] layout; nothing past the end
+    nodes, R = 3, 16
+    banner("spill write probe", C, b2)
+    buf = torch.full((nodes * R * C + 64, 4), -7.0, device="cuda")
+    fstat.spill_write_probe(buf, nodes, R, C, b2)
+    torch.cuda.synchronize()
+    got = buf.cpu().numpy()
+    i = np.arange(R * C)
+    if b2:
+        r = (i % (R * b2)) // b2
+    else:
+        r = i // C
+    for n in range(nodes):
+        blk = got[n * R * C:(n + 1) * R * C]
+        assert np.array_equal(blk[:, 0], r) and np.all(blk[:, 1] == n)
+        assert np.all(blk[:, 2] == 0.0) and np.all(blk[:, 3] == 1.0)
+    assert np.all(got[nodes * R * C:] == -7.0)
+
+
 @pytest.mark.parametrize("blocks", [0, 3])
 def test_copy_probe_copies(blocks):
     banner("copy probe", blocks)

@@ -59,6 +59,8 @@ def parse():
                     help="append to FILE one JSON line per node chunk of every timed step (the chunk's node "
                          "range, the place a resumed run restarts from, its HIP-event time and nodes/s), then "
                          "the result line")
+    ap.add_argument("--leg", choices=("uneven_segments", "large6d", "refinement"), default=None,
+                    help="run one of the other workloads alone and print its JSON object (for profiling)")
     ap.add_argument("--refine-counters", action="store_true",
                     help="short run for FP64 instruction counters: one F + gradient call (fstat_grad) on the "
                          "4096 refinement candidates")
@@ -479,6 +481,10 @@ def main():
         return
     if args.refine_counters:
         refine_leg(reps=1)
+        return
+    if args.leg:
+        leg = {"uneven_segments": uneven_leg, "large6d": large6d_leg, "refinement": refine_leg}[args.leg]
+        print(json.dumps({args.leg: leg()}), flush=True)
         return
     import numpy as np
     import torch

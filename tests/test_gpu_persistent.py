@@ -44,10 +44,10 @@ def _nodes(sig):
     return nodes[np.random.default_rng(75).permutation(len(nodes))]
 
 
-def _plan(segs, launch, autotune=False):
+def _plan(segs, launch, autotune=False, interp=fstat.LINEAR_UP2):
     specs = [fstat.SegmentSpec(x=s.x, dt=s.dt, n_days=s.n_days, t0=s.t0, mask=s.mask, f_ref=s.f_ref,
                                sigma2=s.sigma2, nfft=s.nfft) for s in segs]
-    return fstat.Plan(specs, fstat.detector_spec(DET), fstat.ephemeris_spec(EPH), interp=fstat.LINEAR_UP2,
+    return fstat.Plan(specs, fstat.detector_spec(DET), fstat.ephemeris_spec(EPH), interp=interp,
                       prec=fstat.FP32, device=0, autotune=autotune, launch=launch)
 
 
@@ -135,6 +135,25 @@ def test_persistent_graph_replays(case):
     gm.close()
     gx.close()
     plan.status()
+
+
+@pytest.mark.parametrize("interp", [fstat.NEAREST, fstat.CUBIC_UP2])
+def test_persistent_equals_passes_other_interpolations(case, interp):
+    # the sky-record tiles of the other two resampling modes (Sec. VI A)
+    segs, sig, nodes, ref = case
+    banner("persistent interp", interp)
+    sub = nodes[::3]
+    want = _plan(segs, fstat.LAUNCH_PASSES, interp=interp)
+    F0 = want.grid_map(sub, 0, K_HI).clone()
+    m0, k0 = [t.clone() for t in want.grid_max(sub, 0, K_HI)]
+    del want
+    plan = _plan(segs, fstat.LAUNCH_PERSISTENT, interp=interp)
+    F = plan.grid_map(sub, 0, K_HI)
+    m, k = plan.grid_max(sub, 0, K_HI)
+    torch.cuda.synchronize()
+    plan.status()
+    assert torch.equal(F, F0) and torch.equal(m, m0) and torch.equal(k, k0)
+    assert not torch.equal(F, ref[0][::3])  # a different resampling does change the map
 
 
 def test_an_expired_wait_stops_the_kernel_and_is_reported(case, monkeypatch):
